@@ -1,0 +1,116 @@
+"""Pins of the HOPM oracle: exact rank-1 recovery, the matrix case against
+the SVD, monotonicity, stationarity, Algorithm 1's contraction count and the
+streamed-memory model Eq. (3).  CPU only."""
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+from oracle import hopm as H
+from oracle import tvc as O
+from paper_2501_03121_amd import synth
+
+GOLDEN = Path(__file__).parent / "golden"
+
+
+@pytest.mark.parametrize("dims", [(6, 5, 4), (3, 4, 5, 2), (4, 3, 3, 2, 3)])
+def test_exact_rank1_one_sweep(dims):
+    a = synth.unit_vectors(dims, 1)
+    T = np.ones(())
+    for v in a:
+        T = np.multiply.outer(T, v)
+    x0 = synth.unit_vectors(dims, 3)
+    r = H.hopm(7.5 * T, x0, sweeps=1)
+    assert abs(r.lam - 7.5) < 1e-12
+    for x, v in zip(r.xs, a):
+        assert abs(abs(np.dot(x, v)) - 1.0) < 1e-12
+
+
+def test_matrix_case_is_top_singular_triple():
+    A = synth.normal((12, 9), 5)
+    A += 6.0 * np.outer(synth.unit_vectors([12], 6)[0], synth.unit_vectors([9], 7)[0])
+    r = H.hopm(A, synth.unit_vectors((12, 9), 8), tol=1e-13, max_sweeps=5000)
+    U, S, Vt = np.linalg.svd(A)
+    assert abs(r.lam - S[0]) < 1e-10 * S[0]
+    assert abs(abs(np.dot(r.xs[0], U[:, 0])) - 1) < 1e-10
+    assert abs(abs(np.dot(r.xs[1], Vt[0])) - 1) < 1e-10
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_norms_monotone_and_stationary(seed):
+    dims = (9, 7, 8)
+    A = synth.normal(dims, seed)
+    r = H.hopm(A, synth.unit_vectors(dims, seed + 3), tol=1e-12, max_sweeps=3000)
+    norms = np.array(r.norms)
+    assert np.all(np.diff(norms) >= -1e-12 * norms[1:])
+    for j in range(3):
+        y = H.leave_one_out(A, r.xs, j)
+        assert np.linalg.norm(y - r.lam * r.xs[j]) < 1e-9 * r.lam
+
+
+@pytest.mark.parametrize("d", [2, 3, 4, 5, 6])
+def test_algorithm1_matches_canonical_and_counts(d):
+    dims = tuple([3, 4, 2, 3, 2, 3][:d])
+    A = synth.normal(dims, 11)
+    x0 = synth.unit_vectors(dims, 12)
+    c = H.hopm(A, x0, sweeps=4)
+    a = H.dhopm3(A, x0, sweeps=4)
+    for u, v in zip(c.xs, a.xs):
+        np.testing.assert_allclose(u, v, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(c.norms, a.norms, rtol=1e-12)
+    assert c.tvcs == 4 * d * (d - 1)
+    assert a.tvcs == 4 * (d - 1) * (d + 2) // 2 == 4 * H.tvcs_per_sweep_dhopm3(d)
+    # the paper states the saving as (d-1)(d-2)/2 contractions per sweep
+    assert (c.tvcs - a.tvcs) // 4 == (d - 1) * (d - 2) // 2
+
+
+@pytest.mark.parametrize("n,d", [(5, 2), (4, 3), (3, 4), (3, 5), (2, 6)])
+def test_eq3_streamed_memory(n, d):
+    dims = (n,) * d
+    r = H.hopm(synth.normal(dims, 21), synth.unit_vectors(dims, 22), sweeps=1)
+    assert r.touched == d * H.m_seq(n, d)
+    a = H.dhopm3(synth.normal(dims, 21), synth.unit_vectors(dims, 22), sweeps=1)
+    assert a.touched == H.dhopm3_touched(n, d)
+
+
+def test_streamed_ratio_fig2():
+    # The paper reads about 1.5x saving for the order-3 and roughly fivefold for
+    # the order-10 tensor of Table 1 (Fig. 2(b), one process).
+    r3 = H.streamed_ratio(979, 3)
+    r10 = H.streamed_ratio(8, 10)
+    assert 1.45 < r3 < 1.55
+    assert 4.5 < r10 < 5.5
+
+
+def test_table1_sizes():
+    rows = [ln.split() for ln in (GOLDEN / "table1_hypersquare.txt").read_text().splitlines()
+            if ln and not ln.startswith("#")]
+    gbs = []
+    for d, n, gb in rows:
+        if d == "avg":
+            assert abs(np.mean(gbs) - float(gb)) < 0.005
+            continue
+        size = int(n) ** int(d) * 8 / 1e9
+        assert round(size, 2) == float(gb)
+        gbs.append(float(gb))
+
+
+def test_planted_tiny_config_recovers():
+    dims = (64, 64, 64)
+    A, a = synth.planted_rank1(dims, 5.0, 0.01, 100)
+    r = H.hopm(A, synth.unit_vectors(dims, 103), sweeps=20)
+    assert abs(r.lam - 5.0) < 0.05
+    for x, v in zip(r.xs, a):
+        assert abs(np.dot(x, v)) > 0.9999
+
+
+def test_degenerate_zero_tensor():
+    with pytest.raises(H.DegenerateError):
+        H.hopm(np.zeros((3, 4, 2)), synth.unit_vectors((3, 4, 2), 0), sweeps=1)
+
+
+def test_lambda_is_full_contraction():
+    dims = (5, 4, 6)
+    A = synth.normal(dims, 31)
+    r = H.hopm(A, synth.unit_vectors(dims, 32), sweeps=3)
+    assert abs(O.contract_all(A, r.xs, range(3)) - r.lam) < 1e-12 * r.lam
