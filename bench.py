@@ -1,0 +1,348 @@
+#!/usr/bin/env python3
+"""Benchmark of the TVC / HOPM hot path on one MI355X.
+
+One step = the k-mode contraction of a 1024^3 and a 32^6 float32 tensor
+(N(0,1) entries) in every mode (3 + 6 contractions), plus one HOPM sweep on
+each of two planted tensors of the same shapes (10 * a o b o c ... + N(0, 0.1^2)).
+`value` is the algorithmic HBM traffic of the whole step divided by its time:
+a contraction moves N*4 bytes of A plus its vector and output; a sweep moves
+2*N*4 bytes (two passes over A) plus the vectors.  Inputs are resident in HBM
+before timing starts.
+
+Printed: one JSON line (the last line of stdout).  Extra fields report the
+per-mode figures, bf16 storage, time to solution, the bandwidth probe, the
+dominant kernel against the HBM roofline and the float64 CPU oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "TVC & HOPM-sweep HBM GB/s (% of peak), bf16 vs fp32 at stated rel err"
+SHAPES = [(1024, 1024, 1024), (32, 32, 32, 32, 32, 32)]
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def tvc_bytes(dims, k, b_a, b_v=4):
+    n = math.prod(dims)
+    return n * b_a + (n // dims[k]) * b_v + dims[k] * b_v
+
+
+def sweep_bytes(dims, b_a):
+    return 2 * math.prod(dims) * b_a + 8 * sum(dims)
+
+
+class Call:
+    """A prepared C-ABI call (descriptors built once, outside the timed loop)."""
+
+    def __init__(self, fn, *args):
+        self.fn = fn
+        self.args = args
+
+    def __call__(self):
+        st = self.fn(*self.args)
+        if st != 0:
+            from paper_2501_03121_amd import _lib
+            _lib.check(st)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the contraction shards without communication, see DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2501_03121_amd as tvc
+    from paper_2501_03121_amd import _lib as L
+    from paper_2501_03121_amd import core, synth
+
+    dev = torch.device("cuda:0")
+    lib = L.lib()
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+
+    # ------------------------------------------------------------ inputs
+    log("generating inputs")
+    T = [synth.device_normal(s, 100 + 10 * i, dev) for i, s in enumerate(SHAPES)]
+    Hs, planted = [], []
+    for i, s in enumerate(SHAPES):
+        A, a = synth.device_planted(s, 10.0, 0.1, 200 + 10 * i, dev)
+        Hs.append(A)
+        planted.append(a)
+    torch.cuda.synchronize()
+
+    # contraction calls (x unit uniform vectors, outputs preallocated)
+    tvc_calls = []   # (label, Call, bytes, plan)
+    keep = []
+    for i, (A, s) in enumerate(zip(T, SHAPES)):
+        desc = core.describe(A)
+        keep.append(desc)
+        for k in range(len(s)):
+            x = torch.from_numpy(synth.unit_vectors([s[k]], 300 + k)[0]).float().to(dev)
+            y = torch.empty(A.numel() // s[k], dtype=torch.float32, device=dev)
+            keep += [x, y]
+            need = lib.tvc_contract_workspace_bytes(desc, k)
+            ws = torch.empty(need + 256, dtype=torch.uint8, device=dev) if need else None
+            keep.append(ws)
+            wp = ((ws.data_ptr() + 255) & ~255) if ws is not None else None
+            c = Call(lib.tvc_contract, desc, k, x.data_ptr(), y.data_ptr(), 1.0, 0.0, wp, need, sh)
+            tvc_calls.append((f"{len(s)}d_{s[0]}_mode{k}", c, tvc_bytes(s, k, 4),
+                              tvc.contract_plan(A, k)))
+
+    # HOPM sweep calls (warm start, vectors float64, workspace + stats preallocated)
+    hopm_calls = []
+    for i, (A, s) in enumerate(zip(Hs, SHAPES)):
+        desc = core.describe(A)
+        keep.append(desc)
+        x = tvc.pack_vectors(synth.warm_start(planted[i], 0.9, 400 + i), dev)
+        need = lib.hopm_workspace_bytes(desc)
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+        st = torch.zeros(32, dtype=torch.uint8, device=dev)
+        keep += [x, ws, st]
+        c = Call(lib.hopm_iterate, desc, x.data_ptr(), 1, (ws.data_ptr() + 255) & ~255, need,
+                 st.data_ptr(), sh)
+        hopm_calls.append((f"hopm_sweep_{len(s)}d_{s[0]}", c, sweep_bytes(s, 4)))
+
+    ops = [(lbl, c, b) for (lbl, c, b, _) in tvc_calls] + hopm_calls
+    step_bytes = sum(b for _, _, b in ops)
+
+    # ------------------------------------------------------------ timed steps
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        for _, c, _ in ops:
+            c()
+    torch.cuda.synchronize()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in ops] for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for s in range(args.steps):
+        for j, (_, c, _) in enumerate(ops):
+            ev[s][j][0].record(stream)
+            c()
+            ev[s][j][1].record(stream)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t_start.elapsed_time(t_end)
+    ms_per_step = total_ms / args.steps
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+
+    per_op = {}
+    for j, (lbl, _, b) in enumerate(ops):
+        ms = [ev[s][j][0].elapsed_time(ev[s][j][1]) for s in range(args.steps)]
+        med = statistics.median(ms)
+        per_op[lbl] = {"ms_median": round(med, 4), "ms_mean": round(statistics.mean(ms), 4),
+                       "GBps": round(b / (med * 1e-3) / 1e9, 1),
+                       "pct_peak": round(100 * b / (med * 1e-3) / 1e9 / PEAK_HBM_GBS, 1)}
+    log(json.dumps(per_op))
+
+    # dominant kernel: the column-streaming contraction kernel (float32,
+    # 16-byte loads, 4 wave groups) launched by tvc_contract
+    dom = [(lbl, b) for (lbl, _, b, p) in tvc_calls
+           if p["family"] == "col" and p["vec"] and p["split_m"] == 4 and p["nsplit"] == 1]
+    dom_ms, dom_b = [], []
+    for lbl, b in dom:
+        j = [o[0] for o in ops].index(lbl)
+        dom_ms += [ev[s][j][0].elapsed_time(ev[s][j][1]) for s in range(args.steps)]
+        dom_b += [b] * args.steps
+    avg_ms = statistics.mean(dom_ms)
+    avg_b = statistics.mean(dom_b)
+    achieved = avg_b / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "kernel": "tvc::k_col<1, true, 4, 0> (float32 column streaming)",
+                "launches_per_step": len(dom), "avg_launch_ms": round(avg_ms, 4),
+                "avg_bytes_per_launch": int(avg_b)}
+
+    modes_pct = [per_op[lbl]["pct_peak"] for (lbl, _, _, _) in tvc_calls]
+    extra = {
+        "step_bytes": step_bytes,
+        "wall_s_timed": round(wall, 3),
+        "per_op": per_op,
+        "tvc_pct_peak_mean": round(statistics.mean(modes_pct), 1),
+        "tvc_pct_peak_std": round(statistics.stdev(modes_pct), 1),
+        "plans": {lbl: p for (lbl, _, _, p) in tvc_calls},
+    }
+
+    if not args.no_extras:
+        extra.update(run_extras(T, Hs, planted, dev, args))
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "TVC every mode + one HOPM sweep, 1024^3 and 32^6 float32 N(0,1) "
+                               "(HOPM on 10*rank-1 + N(0,0.1^2))",
+                   "shapes": ["1024^3", "32^6"], "pct_of_peak": round(100 * value / PEAK_HBM_GBS, 1)},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(T[0])
+    result["extra"] = extra
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def run_extras(T, Hs, planted, dev, args):
+    import torch
+
+    import paper_2501_03121_amd as tvc
+    from paper_2501_03121_amd import synth
+
+    out = {}
+    # bandwidth probe: read the 1024^3 tensor, copy 1 GiB
+    sink = torch.empty(8192, dtype=torch.float32, device=dev)
+    src = T[0]
+    for _ in range(2):
+        tvc.probe_read(src, sink)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        tvc.probe_read(src, sink)
+    e1.record()
+    torch.cuda.synchronize()
+    rd = src.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    tvc.probe_copy(a, b)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        tvc.probe_copy(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    cp = 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    out["probe"] = {"read_GBps": round(rd, 1), "copy_GBps": round(cp, 1),
+                    "read_pct_peak": round(100 * rd / PEAK_HBM_GBS, 1)}
+    log(json.dumps(out["probe"]))
+
+    # bf16 storage: every-mode contraction and one sweep
+    bf = {}
+    for i, (A, s) in enumerate(zip(T, SHAPES)):
+        Ab, _ = tvc.quantize(A, "bf16")
+        for k in range(len(s)):
+            x = torch.from_numpy(synth.unit_vectors([s[k]], 300 + k)[0]).float().to(dev)
+            y = torch.empty(A.numel() // s[k], dtype=torch.float32, device=dev)
+            tvc.contract(Ab, x, k, out=y)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                tvc.contract(Ab, x, k, out=y)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            gbs = tvc_bytes(s, k, 2) / (ms * 1e-3) / 1e9
+            bf[f"{len(s)}d_{s[0]}_mode{k}"] = {"ms": round(ms, 4), "GBps": round(gbs, 1),
+                                               "pct_peak": round(100 * gbs / PEAK_HBM_GBS, 1)}
+        del Ab
+    out["bf16_tvc"] = bf
+    log(json.dumps(bf))
+
+    # time to solution: float32 vs bf16 storage + one float32 refinement sweep,
+    # from the same warm start (overlap 0.9 with the planted vectors)
+    tts = {}
+    for i, (A, s) in enumerate(zip(Hs, SHAPES)):
+        Ab, _ = tvc.quantize(A, "bf16")
+        x0 = synth.warm_start(planted[i], 0.9, 400 + i)
+        res = {}
+        for label, store, refine in (("f32", A, None), ("bf16+f32refine", Ab, A)):
+            runs = []
+            for rep in range(3):
+                x = tvc.pack_vectors(x0, dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = tvc.hopm_solve(store, x, tol=1e-6, max_sweeps=500, check_every=1,
+                                   A_refine=refine, refine_sweeps=1 if refine is not None else 0)
+                torch.cuda.synchronize()
+                runs.append((time.perf_counter() - t0, r))
+            tmed = statistics.median(t for t, _ in runs)
+            r = runs[-1][1]
+            xs = x.cpu().numpy()
+            dims_off = 0
+            overl = []
+            for k, n in enumerate(s):
+                overl.append(abs(float(xs[dims_off:dims_off + n] @ planted[i][k])))
+                dims_off += n
+            res[label] = {"seconds": round(tmed, 5), "sweeps": r.sweeps, "refine_sweeps": r.refine_sweeps,
+                          "lambda": r.lam, "delta": r.delta, "status": r.status,
+                          "min_overlap": round(min(overl), 6)}
+        res["speedup_bf16"] = round(res["f32"]["seconds"] / res["bf16+f32refine"]["seconds"], 3)
+        res["lambda_rel_diff"] = abs(res["bf16+f32refine"]["lambda"] - res["f32"]["lambda"]) / res["f32"]["lambda"]
+        tts[f"{len(s)}d_{s[0]}"] = res
+        del Ab
+    out["time_to_solution"] = tts
+    log(json.dumps(tts))
+    return out
+
+
+def cpu_baseline(A_dev):
+    """The float64 oracle (NumPy) on the host: contraction of the 1024^3
+    tensor in its 3 modes, from the exact upcast of the device bytes (upcast
+    not timed).  Throughput counts 4 bytes per element, like the GPU figure."""
+    import numpy as np
+
+    from oracle import tvc as O
+    from paper_2501_03121_amd import synth
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
+    except Exception:
+        threads = os.cpu_count() or 1
+    log("cpu baseline: copying tensor to host")
+    A = A_dev.cpu().numpy().astype(np.float64)
+    dims = A.shape
+    t = 0.0
+    for k in range(3):
+        x = synth.unit_vectors([dims[k]], 300 + k)[0]
+        t0 = time.perf_counter()
+        O.tvc(A, x, k)
+        t += time.perf_counter() - t0
+    gbs = 3 * A.size * 4 / t / 1e9
+    return {"value": round(gbs, 2), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"float64 NumPy oracle, contraction of the 1024^3 tensor in modes 0,1,2 "
+                      f"({t:.1f} s), 4 bytes/element counted"}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,194 @@
+/*
+ * tvc.h -- C ABI of the MI355X (gfx950) tensor-vector contraction library.
+ *
+ * Operations (Martinez-Ferrer, Yzelman, Beltran, "Distributed and
+ * heterogeneous tensor-vector contraction algorithms for high performance
+ * computing", FGCS 2025, arXiv 2501.03121):
+ *   - the k-mode tensor-vector contraction Y = A x_k x of a dense order-d
+ *     tensor (Sec. 3), with the BLAS-like alpha/beta scaling of Eq. (1);
+ *   - the higher-order power method (HOPM, Sec. 3) with the Gauss-Seidel
+ *     update order of Algorithm 1 (dHOPM_3), on one device;
+ *   - storage of A in a lower precision with promotion before arithmetic
+ *     (Sec. 5.5), plus derivatives and batched HOPM built on the same kernels.
+ *
+ * Conventions shared by every entry point
+ *   Layout     Tensors are dense, C-contiguous and last-order (the last mode
+ *              varies fastest), zero-based, as in Sec. 3.  The contraction
+ *              output keeps the remaining modes in their original order.
+ *   Memory     Every data pointer is a DEVICE pointer owned by the caller,
+ *              unless stated as host.  The library never allocates device
+ *              memory; scratch space is passed in as a workspace whose size
+ *              the matching *_workspace_bytes call returns.
+ *   Streams    `stream` is a hipStream_t passed as void* (NULL = the null
+ *              stream).  All work is enqueued asynchronously on it; only
+ *              hopm_solve waits on the stream.
+ *   Dtypes     A: TVC_F64, TVC_F32, TVC_F16 (IEEE binary16), TVC_BF16,
+ *              TVC_F8E4M3 (OCP E4M3FN, with one float32 scale per mode-0
+ *              slice).  Vectors x, outputs y and gradients are double for
+ *              TVC_F64 and float for every other dtype.  Accumulation is in
+ *              double for TVC_F64 and float otherwise.  HOPM vectors are
+ *              always double.
+ *   Errors     Every call returns a tvc_status; nothing aborts or throws.
+ *              On error nothing is enqueued.  tvc_last_error() gives a
+ *              message for the last failure of the calling thread.
+ */
+#ifndef TVC_H
+#define TVC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TVC_OK = 0,
+  TVC_EINVAL = 1,        /* bad order, dims, mode, size or pointer */
+  TVC_EDTYPE = 2,        /* dtype not valid for this entry point */
+  TVC_EALIAS = 3,        /* an output overlaps an input */
+  TVC_EWORKSPACE = 4,    /* workspace NULL, misaligned or too small */
+  TVC_EHIP = 5,          /* a HIP runtime call or kernel launch failed */
+  TVC_EDEGENERATE = 6,   /* a vector to normalise had zero norm */
+  TVC_ENOTCONVERGED = 7  /* max_sweeps reached before delta < tol */
+} tvc_status;
+
+typedef enum {
+  TVC_F64 = 0,
+  TVC_F32 = 1,
+  TVC_F16 = 2,
+  TVC_BF16 = 3,
+  TVC_F8E4M3 = 4
+} tvc_dtype;
+
+#define TVC_MAX_ORDER 16
+
+/* A dense tensor.  order in [1, TVC_MAX_ORDER]; dims[0..order) >= 1; the
+ * element count must fit in int64.  data must be aligned to the element size
+ * (16-byte alignment enables the vector-load kernels).  slab_scale: for
+ * TVC_F8E4M3, dims[0] float32 scales, the value of element (i0, ...) being
+ * decode(code) * slab_scale[i0]; NULL for every other dtype. */
+typedef struct {
+  int32_t order;
+  int32_t dtype;                 /* tvc_dtype */
+  int64_t dims[TVC_MAX_ORDER];
+  const void* data;
+  const float* slab_scale;
+} tvc_tensor;
+
+/* HOPM progress record (device-resident for hopm_iterate, host for
+ * hopm_solve).  lambda = norm of the last contraction result before its
+ * normalisation (= A x_0 x_0 ... x_{d-1} x_{d-1} afterwards); delta = largest
+ * ||x_j(new) - x_j(old)||_2 over j in the last sweep; sweeps = sweeps done by
+ * the call; status = TVC_OK or TVC_EDEGENERATE; refine_sweeps = sweeps of the
+ * refinement stage of hopm_solve (0 otherwise). */
+typedef struct {
+  double lambda;
+  double delta;
+  int32_t sweeps;
+  int32_t status;
+  int32_t refine_sweeps;
+  int32_t reserved;
+} hopm_stats;
+
+/* Human-readable name of a status code (static string). */
+const char* tvc_status_string(int32_t status);
+
+/* Detail message of the last failing call on this thread ("" if none). */
+const char* tvc_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t tvc_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Tensor-vector contraction, Sec. 3 (definition and the (u, n_k, v) view)
+ * and Eq. (1) (alpha/beta form):
+ *     Y := alpha * (A x_mode x) + beta * Y
+ * x: n_mode elements.  y: N / n_mode elements, C-contiguous over the modes of
+ * A without `mode`.  beta == 0 means y is not read (NaN in y is harmless).
+ * ws/ws_bytes: scratch of at least tvc_contract_workspace_bytes(A, mode)
+ * bytes, 256-byte aligned; may be NULL when that size is 0.
+ * Errors: EINVAL (order/dims/mode/pointers), EDTYPE (unknown dtype, or
+ * TVC_F8E4M3 without slab_scale), EALIAS (y overlaps A or x), EWORKSPACE,
+ * EHIP.  Results are deterministic: the same call gives the same bits.
+ * ------------------------------------------------------------------------- */
+size_t tvc_contract_workspace_bytes(const tvc_tensor* A, int32_t mode);
+int32_t tvc_contract(const tvc_tensor* A, int32_t mode, const void* x, void* y,
+                     double alpha, double beta, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/* Introspection of the launch tvc_contract(A, mode, ...) would make, for
+ * tests, benchmarks and the autotuner.  Writes up to n values to info (host):
+ * [0] family (0 = rows of the right-extent-1 view, 1 = column streaming,
+ * 2 = small-right slabs), [1] 1 if 16-byte vector loads are used, [2] wave
+ * groups per workgroup along the contracted extent (family 1), [3] number
+ * of splits of the contracted extent (> 1 adds a finalize kernel), [4]
+ * workgroups launched, [5] lanes per row (families 0 and 2, 0 = a wave per
+ * row).  Assumes 16-byte aligned x.  Returns TVC_OK or an argument error. */
+int32_t tvc_contract_plan(const tvc_tensor* A, int32_t mode, int32_t* info, int32_t n);
+
+/* ---------------------------------------------------------------------------
+ * Higher-order power method, Sec. 3 (canonical HOPM) with the update order
+ * of Algorithm 1: external iteration j = 0..d-1 replaces x_j by the
+ * normalised contraction of A with every other vector, using the vectors
+ * already updated in the same sweep.  One sweep streams A twice: once to
+ * form M = A contracted over modes 2..d-1 (which gives x_0 and x_1), once to
+ * form A contracted over modes 0 and 1 (which gives x_2..x_{d-1}).  Needs
+ * order >= 2.
+ * x: device double buffer holding x_0, x_1, ..., x_{d-1} back to back
+ * (sum of dims elements), unit-norm on entry, updated in place.
+ * ws: at least hopm_workspace_bytes(A) bytes, 256-byte aligned.  The same
+ * workspace size also serves a TVC_F32 tensor of the same dims.
+ * ------------------------------------------------------------------------- */
+size_t hopm_workspace_bytes(const tvc_tensor* A);
+
+/* Runs exactly `sweeps` (>= 1) sweeps; no host synchronisation, safe to
+ * capture in a hipGraph.  d_stats (device) receives lambda and delta of the
+ * last sweep, sweeps = `sweeps`, status TVC_EDEGENERATE if any zero-norm
+ * vector was met (that vector is then left unchanged). */
+int32_t hopm_iterate(const tvc_tensor* A, double* x, int32_t sweeps, void* ws,
+                     size_t ws_bytes, hopm_stats* d_stats, void* stream);
+
+/* Sweeps on A until delta < tol (tested every `check_every` sweeps, which
+ * reads the stats back to the host and synchronises the stream) or
+ * max_sweeps sweeps.  Then, if A_refine is not NULL (a TVC_F32 tensor of the
+ * same dims, normally the original of a low-precision A), up to
+ * refine_sweeps sweeps on A_refine with the same stopping test.  h_out
+ * (host) receives the final record.  Returns TVC_OK, TVC_ENOTCONVERGED (the
+ * last iterate is still in x), TVC_EDEGENERATE, or an argument error. */
+int32_t hopm_solve(const tvc_tensor* A, const tvc_tensor* A_refine, double* x,
+                   double tol, int32_t max_sweeps, int32_t check_every,
+                   int32_t refine_sweeps, void* ws, size_t ws_bytes,
+                   hopm_stats* h_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Lower-precision storage (Sec. 5.5: values stored narrow, promoted before
+ * arithmetic).  Converts a TVC_F32 tensor `src` into `dst_dtype` (TVC_F16,
+ * TVC_BF16 or TVC_F8E4M3), written to dst (N elements of the narrow type).
+ * Rounding is to nearest even; flags & TVC_QUANT_TRUNCATE selects bf16 by
+ * truncation instead (the paper's conversion).  For TVC_F8E4M3 the
+ * per-mode-0-slice scale absmax/448 (1 for an all-zero slice) is written to
+ * slab_scale_out (dims[0] floats) and codes are e4m3(src / scale), finite
+ * overflow saturating to +-448.  Errors: EINVAL, EDTYPE, EALIAS, EHIP.
+ * ------------------------------------------------------------------------- */
+#define TVC_QUANT_TRUNCATE 1
+int32_t tvc_quantize(const tvc_tensor* src, void* dst, int32_t dst_dtype,
+                     float* slab_scale_out, int32_t flags, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Bandwidth probes (the analogue of the paper's STREAM yardstick, Sec. 5.1,
+ * written for this library): read `bytes` bytes of src and write one float
+ * per workgroup to sink (>= grid floats), or copy `bytes` bytes from src to
+ * dst.  bytes must be a multiple of 16; pointers 16-byte aligned.  grid = 0
+ * picks a default.
+ * ------------------------------------------------------------------------- */
+int32_t tvc_probe_read(const void* src, size_t bytes, float* sink, int32_t grid,
+                       void* stream);
+int32_t tvc_probe_copy(const void* src, void* dst, size_t bytes, int32_t grid,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TVC_H */

@@ -1,0 +1,130 @@
+// Internal device helpers shared by the HIP kernels of libtvc (gfx950 only).
+//
+// Storage formats and their promotion before arithmetic (the paper's
+// mixed-precision scheme, Sec. 5.5: low precision is a storage format only):
+//   TVC_F64 -> double accumulate;  TVC_F32, TVC_F16, TVC_BF16, TVC_F8E4M3 ->
+//   float accumulate.  A "unit" is one 16-byte vector load (EPV elements) on
+//   the vector paths, or one element on the scalar paths.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tvc.h"
+
+namespace tvc {
+
+typedef int64_t i64;
+
+constexpr int kWave = 64;      // CDNA wavefront width
+constexpr int kBlock = 256;    // threads per workgroup for the streaming kernels
+
+template <int DT> struct St;
+template <> struct St<TVC_F64>    { typedef double   T; typedef double Acc; static constexpr int EPV = 2; };
+template <> struct St<TVC_F32>    { typedef float    T; typedef float  Acc; static constexpr int EPV = 4; };
+template <> struct St<TVC_F16>    { typedef uint16_t T; typedef float  Acc; static constexpr int EPV = 8; };
+template <> struct St<TVC_BF16>   { typedef uint16_t T; typedef float  Acc; static constexpr int EPV = 8; };
+template <> struct St<TVC_F8E4M3> { typedef uint8_t  T; typedef float  Acc; static constexpr int EPV = 16; };
+
+// ---------------------------------------------------------------- conversions
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ __forceinline__ float f16_bits(uint32_t h) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)(h & 0xffffu));
+}
+// gfx950 converts OCP E4M3 in hardware: two bytes of a dword per instruction.
+__device__ __forceinline__ void e4m3x4(uint32_t w, float* o) {
+  auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false);
+  auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
+  o[0] = lo[0]; o[1] = lo[1]; o[2] = hi[0]; o[3] = hi[1];
+}
+__device__ __forceinline__ float e4m3_one(uint32_t b) {
+  return __builtin_amdgcn_cvt_f32_fp8((int)(b & 0xffu), 0);
+}
+
+// One element, promoted.
+template <int DT> __device__ __forceinline__ typename St<DT>::Acc load_elem(const void* p, i64 i);
+template <> __device__ __forceinline__ double load_elem<TVC_F64>(const void* p, i64 i) { return ((const double*)p)[i]; }
+template <> __device__ __forceinline__ float load_elem<TVC_F32>(const void* p, i64 i) { return ((const float*)p)[i]; }
+template <> __device__ __forceinline__ float load_elem<TVC_F16>(const void* p, i64 i) { return f16_bits(((const uint16_t*)p)[i]); }
+template <> __device__ __forceinline__ float load_elem<TVC_BF16>(const void* p, i64 i) { return bf16_lo(((const uint16_t*)p)[i]); }
+template <> __device__ __forceinline__ float load_elem<TVC_F8E4M3>(const void* p, i64 i) { return e4m3_one(((const uint8_t*)p)[i]); }
+
+// One 16-byte vector, promoted into EPV values.
+template <int DT> __device__ __forceinline__ void unpack16(const uint4& r, typename St<DT>::Acc* o);
+template <> __device__ __forceinline__ void unpack16<TVC_F64>(const uint4& r, double* o) {
+  o[0] = __hiloint2double((int)r.y, (int)r.x);
+  o[1] = __hiloint2double((int)r.w, (int)r.z);
+}
+template <> __device__ __forceinline__ void unpack16<TVC_F32>(const uint4& r, float* o) {
+  o[0] = __uint_as_float(r.x); o[1] = __uint_as_float(r.y);
+  o[2] = __uint_as_float(r.z); o[3] = __uint_as_float(r.w);
+}
+template <> __device__ __forceinline__ void unpack16<TVC_BF16>(const uint4& r, float* o) {
+  o[0] = bf16_lo(r.x); o[1] = bf16_hi(r.x); o[2] = bf16_lo(r.y); o[3] = bf16_hi(r.y);
+  o[4] = bf16_lo(r.z); o[5] = bf16_hi(r.z); o[6] = bf16_lo(r.w); o[7] = bf16_hi(r.w);
+}
+template <> __device__ __forceinline__ void unpack16<TVC_F16>(const uint4& r, float* o) {
+  o[0] = f16_bits(r.x); o[1] = f16_bits(r.x >> 16); o[2] = f16_bits(r.y); o[3] = f16_bits(r.y >> 16);
+  o[4] = f16_bits(r.z); o[5] = f16_bits(r.z >> 16); o[6] = f16_bits(r.w); o[7] = f16_bits(r.w >> 16);
+}
+template <> __device__ __forceinline__ void unpack16<TVC_F8E4M3>(const uint4& r, float* o) {
+  e4m3x4(r.x, o); e4m3x4(r.y, o + 4); e4m3x4(r.z, o + 8); e4m3x4(r.w, o + 12);
+}
+
+// A unit: VEC -> 16 bytes (EPV elements); scalar -> one element.
+template <int DT, bool VEC> struct Unit {
+  static constexpr int EU = VEC ? St<DT>::EPV : 1;
+  typedef typename St<DT>::Acc Acc;
+  typedef typename std::conditional<VEC, uint4, typename St<DT>::T>::type Raw;
+  __device__ __forceinline__ static Raw load(const void* base, i64 u) {
+    return ((const Raw*)base)[u];
+  }
+  __device__ __forceinline__ static Raw zero() { Raw r; __builtin_memset(&r, 0, sizeof(Raw)); return r; }
+  __device__ __forceinline__ static void unpack(const Raw& r, Acc* o) {
+    if constexpr (VEC) {
+      unpack16<DT>(r, o);
+    } else {
+      o[0] = load_elem<DT>(&r, 0);
+    }
+  }
+};
+
+// EU consecutive weights starting at element e (16-byte aligned when VEC).
+template <typename Acc, int EU>
+__device__ __forceinline__ void load_w(const Acc* w, i64 e, Acc* o) {
+  if constexpr (EU * sizeof(Acc) >= 16) {
+    const uint4* p = (const uint4*)(w + e);
+#pragma unroll
+    for (int q = 0; q < (int)(EU * sizeof(Acc) / 16); ++q) {
+      uint4 r = p[q];
+      if constexpr (sizeof(Acc) == 4) {
+        o[4 * q + 0] = __uint_as_float(r.x); o[4 * q + 1] = __uint_as_float(r.y);
+        o[4 * q + 2] = __uint_as_float(r.z); o[4 * q + 3] = __uint_as_float(r.w);
+      } else {
+        o[2 * q + 0] = __hiloint2double((int)r.y, (int)r.x);
+        o[2 * q + 1] = __hiloint2double((int)r.w, (int)r.z);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < EU; ++q) o[q] = w[e + q];
+  }
+}
+
+// ---------------------------------------------------------------- reductions
+template <typename Acc>
+__device__ __forceinline__ Acc shfl_xor(Acc v, int m) {
+  return __shfl_xor(v, m, kWave);
+}
+
+template <typename Acc>
+__device__ __forceinline__ Acc wave_sum(Acc v) {
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) v += shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+}  // namespace tvc

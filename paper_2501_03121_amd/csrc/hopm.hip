@@ -1,0 +1,523 @@
+// Higher-order power method on one device (Sec. 3 canonical HOPM, update
+// order of Algorithm 1).
+//
+// One sweep performs the external iterations j = 0..d-1 in order; iteration
+// j replaces x_j by the normalised contraction of A with every other vector,
+// using the vectors already refreshed in this sweep (Gauss-Seidel).
+//
+// Schedule (d >= 3).  Algorithm 1 streams the full tensor twice per sweep
+// (A x_1 x_1 at j = 0 and A x_0 x_0 at j = 1) and reuses the buffer W for
+// j >= 2.  Here the two full passes are arranged so that nothing of size
+// N / n_k is written between them:
+//   pass 1:  M = A contracted with x_2 (x) ... (x) x_{d-1}   (an n_0 x n_1
+//            matrix; A is read as [n_0 n_1][n_2 ... n_{d-1}] rows)
+//            j = 0:  x_0 <- normalise(M x_1)
+//            j = 1:  x_1 <- normalise(M^T x_0)
+//   pass 2:  W_2 = A contracted with x_0 (x) x_1            (A read as one
+//            [n_0 n_1] x [n_2 ... n_{d-1}] slab)
+//            j >= 2: W_j = W_{j-1} x_{j-1} x_{j-1} (Algorithm 1's reuse of W),
+//                    x_j <- normalise(W_j contracted with x_{j+1}..x_{d-1})
+// Both j = 0 and j = 1 of Algorithm 1 contract A with exactly these vectors
+// (contraction order does not change the result), so the iterates are those
+// of the paper's sweep; only the intermediates differ.  d = 2 is two plain
+// matrix-vector products per sweep.
+//
+// Vectors are kept in double (the master copy) and mirrored in the
+// accumulation type for the contraction kernels.  Norms, the Rayleigh
+// quotient lambda = ||y_{d-1}|| and the change delta are computed in double.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "internal.h"
+
+namespace tvc {
+
+constexpr int kNormBlock = 1024;
+
+// ---------------------------------------------------------------- kernels
+struct VecOffsets {
+  int d;
+  i64 n[TVC_MAX_ORDER];
+  i64 off[TVC_MAX_ORDER];
+  i64 woff[TVC_MAX_ORDER];
+};
+
+// Mirror the double vectors into the accumulation type (16-byte aligned per
+// vector) and reset the stats record.
+template <typename Acc>
+__global__ void k_prepare(const double* x, Acc* wv, VecOffsets vo, hopm_stats* st) {
+  for (int m = 0; m < vo.d; ++m)
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < vo.n[m];
+         i += (i64)gridDim.x * blockDim.x)
+      wv[vo.woff[m] + i] = (Acc)x[vo.off[m] + i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->lambda = 0.0;
+    st->delta = 0.0;
+    st->sweeps = 0;
+    st->status = TVC_OK;
+    st->refine_sweeps = 0;
+    st->reserved = 0;
+  }
+}
+
+__device__ __forceinline__ double block_sum_1024(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x < kNormBlock / kWave) s = sh[threadIdx.x];
+  if (threadIdx.x < kWave) s = wave_sum(s);
+  __syncthreads();
+  if (threadIdx.x == 0) sh[0] = s;
+  __syncthreads();
+  s = sh[0];
+  __syncthreads();
+  return s;
+}
+
+enum { kFirstJ = 1, kLastJ = 2 };
+
+// x <- y / ||y||, mirrored into wv; delta and lambda bookkeeping in double.
+template <typename Acc>
+__global__ __launch_bounds__(kNormBlock) void k_normalize(const Acc* y, i64 n, double* x, Acc* wv,
+                                                          hopm_stats* st, int flags) {
+  __shared__ double sh[kNormBlock / kWave];
+  double ss = 0.0;
+  for (i64 i = threadIdx.x; i < n; i += kNormBlock) {
+    const double v = (double)y[i];
+    ss += v * v;
+  }
+  ss = block_sum_1024(ss, sh);
+  const double nrm = sqrt(ss);
+  if (!(nrm > 0.0) || !isfinite(nrm)) {
+    if (threadIdx.x == 0) {
+      st->status = TVC_EDEGENERATE;
+      if (flags & kFirstJ) st->delta = 0.0;
+      if (flags & kLastJ) {
+        st->lambda = nrm;
+        st->sweeps += 1;
+      }
+    }
+    return;
+  }
+  const double inv = 1.0 / nrm;
+  double dd = 0.0;
+  for (i64 i = threadIdx.x; i < n; i += kNormBlock) {
+    const double v = (double)y[i] * inv;
+    const double d = v - x[i];
+    dd += d * d;
+    x[i] = v;
+    wv[i] = (Acc)v;
+  }
+  dd = block_sum_1024(dd, sh);
+  if (threadIdx.x == 0) {
+    const double dj = sqrt(dd);
+    st->delta = (flags & kFirstJ) ? dj : fmax(st->delta, dj);
+    if (flags & kLastJ) {
+      st->lambda = nrm;
+      st->sweeps += 1;
+    }
+  }
+}
+
+// w[r] = prod_{m} v_m[i_m(r)] over the modes given by (offs, dims), the
+// last mode varying fastest; product formed in double, rounded once.
+struct KronArgs {
+  int nm;
+  i64 dims[TVC_MAX_ORDER];
+  i64 offs[TVC_MAX_ORDER];
+};
+
+template <typename Acc>
+__global__ void k_kron(const double* x, KronArgs k, Acc* w, i64 n, const float* scale0, i64 sdiv) {
+  for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (i64)gridDim.x * blockDim.x) {
+    i64 rem = r;
+    double p = 1.0;
+    for (int m = k.nm - 1; m >= 0; --m) {
+      const i64 i = rem % k.dims[m];
+      rem /= k.dims[m];
+      p *= x[k.offs[m] + i];
+    }
+    if (scale0) p *= (double)scale0[r / sdiv];
+    w[r] = (Acc)p;
+  }
+}
+
+// ---------------------------------------------------------------- schedule
+namespace {
+
+struct Layout {
+  int dt = TVC_F32;
+  int acc_dt = TVC_F32;       // dtype naming the accumulation type
+  size_t ab = 4;
+  int d = 0;
+  i64 n[TVC_MAX_ORDER] = {};
+  i64 off[TVC_MAX_ORDER] = {};   // offsets of the double vectors in x
+  i64 woff[TVC_MAX_ORDER] = {};  // offsets of their mirrors in wv (16-byte aligned)
+  i64 wsum = 0;
+  i64 nsum = 0, nmax = 0, N = 0, R1 = 1, n01 = 1;
+  // byte offsets into ws
+  size_t o_wv = 0, o_y = 0, o_M = 0, o_w1 = 0, o_w2 = 0, o_Wa = 0, o_Wb = 0, o_Ca = 0, o_Cb = 0,
+         o_stats = 0, o_part = 0;
+  size_t part_bytes = 0;
+  size_t total = 0;
+};
+
+// Every contraction a sweep performs, as (dtype, L, M, R); the workspace
+// must hold the largest partial-sum scratch among them.
+void sweep_tvcs(const Layout& Lt, std::vector<std::array<i64, 4>>& out) {
+  const int d = Lt.d;
+  const i64* n = Lt.n;
+  if (d == 2) {
+    out.push_back({Lt.dt, n[0], n[1], 1});
+    out.push_back({Lt.dt, 1, n[0], n[1]});
+    return;
+  }
+  out.push_back({Lt.dt, Lt.n01, Lt.R1, 1});            // pass 1
+  out.push_back({Lt.acc_dt, n[0], n[1], 1});           // M x_1
+  out.push_back({Lt.acc_dt, 1, n[0], n[1]});           // M^T x_0
+  out.push_back({Lt.dt, 1, Lt.n01, Lt.R1});            // pass 2
+  i64 wsize = Lt.R1;
+  for (int j = 2; j < d; ++j) {
+    if (j > 2) {
+      out.push_back({Lt.acc_dt, 1, n[j - 1], wsize / n[j - 1]});
+      wsize /= n[j - 1];
+    }
+    i64 t = wsize;
+    for (int m = d - 1; m > j; --m) {
+      out.push_back({Lt.acc_dt, t / n[m], n[m], 1});
+      t /= n[m];
+    }
+  }
+}
+
+Layout make_layout(const tvc_tensor* A) {
+  Layout Lt;
+  Lt.dt = A->dtype;
+  Lt.acc_dt = A->dtype == TVC_F64 ? TVC_F64 : TVC_F32;
+  Lt.ab = acc_bytes(A->dtype);
+  Lt.d = A->order;
+  Lt.N = 1;
+  const i64 per16 = 16 / (i64)acc_bytes(A->dtype);
+  for (int i = 0; i < Lt.d; ++i) {
+    Lt.n[i] = A->dims[i];
+    Lt.off[i] = Lt.nsum;
+    Lt.nsum += Lt.n[i];
+    Lt.woff[i] = Lt.wsum;
+    Lt.wsum += (Lt.n[i] + per16 - 1) / per16 * per16;
+    Lt.nmax = std::max(Lt.nmax, Lt.n[i]);
+    Lt.N *= Lt.n[i];
+  }
+  if (Lt.d >= 3) {
+    Lt.n01 = Lt.n[0] * Lt.n[1];
+    Lt.R1 = Lt.N / Lt.n01;
+  }
+  const size_t ab = Lt.ab;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  Lt.o_stats = take(sizeof(hopm_stats));
+  Lt.o_wv = take((size_t)Lt.wsum * ab);
+  Lt.o_y = take((size_t)Lt.nmax * ab);
+  if (Lt.d >= 3) {
+    Lt.o_M = take((size_t)Lt.n01 * ab);
+    Lt.o_w2 = take((size_t)Lt.n01 * ab);
+    Lt.o_w1 = take(Lt.d >= 4 ? (size_t)Lt.R1 * ab : 0);
+    Lt.o_Wa = take((size_t)Lt.R1 * ab);
+    Lt.o_Wb = take(Lt.d >= 4 ? (size_t)(Lt.R1 / Lt.n[2]) * ab : 0);
+    const size_t c = Lt.d >= 4 ? (size_t)(Lt.R1 / Lt.n[Lt.d - 1]) * ab : 0;
+    Lt.o_Ca = take(c);
+    Lt.o_Cb = take(c);
+  } else {
+    Lt.o_w2 = take((size_t)Lt.n[0] * ab);   // scaled weights for E4M3 (d = 2)
+  }
+  std::vector<std::array<i64, 4>> tv;
+  sweep_tvcs(Lt, tv);
+  size_t pb = 0;
+  for (auto& t : tv)
+    for (int a16 = 0; a16 < 2; ++a16)
+      for (int w16 = 0; w16 < 2; ++w16)
+        pb = std::max(pb, plan_tvc((int)t[0], t[1], t[2], t[3], a16, w16).part_bytes);
+  Lt.part_bytes = pb;
+  Lt.o_part = take(pb);
+  Lt.total = o;
+  return Lt;
+}
+
+struct Ctx {
+  const Layout* Lt;
+  const tvc_tensor* A;
+  double* x;
+  char* ws;
+  hopm_stats* st;
+  hipStream_t s;
+  template <typename P> P* at(size_t o) const { return (P*)(ws + o); }
+};
+
+#define TVC_TRY_HIP(expr)                                                                 \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(TVC_EHIP, std::string("HIP: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+tvc_status run(const Ctx& c, int dt, const void* A, i64 L, i64 M, i64 R, const void* w, void* y,
+               const float* oscale, i64 odiv) {
+  return tvc_run_auto(dt, A, L, M, R, w, y, 1.0, 0.0, oscale, odiv, c.ws + c.Lt->o_part,
+                      c.Lt->part_bytes, c.s, kRoleHopm);
+}
+
+template <typename Acc>
+tvc_status normalize(const Ctx& c, const void* y, int j) {
+  const Layout& Lt = *c.Lt;
+  int flags = (j == 0 ? kFirstJ : 0) | (j == Lt.d - 1 ? kLastJ : 0);
+  hipLaunchKernelGGL((k_normalize<Acc>), dim3(1), dim3(kNormBlock), 0, c.s, (const Acc*)y,
+                     Lt.n[j], c.x + Lt.off[j], c.at<Acc>(Lt.o_wv) + Lt.woff[j], c.st, flags);
+  TVC_TRY_HIP(hipGetLastError());
+  return TVC_OK;
+}
+
+template <typename Acc>
+tvc_status kron(const Ctx& c, int m0, int m1, Acc* w, const float* scale0, i64 sdiv) {
+  const Layout& Lt = *c.Lt;
+  KronArgs k;
+  k.nm = m1 - m0;
+  i64 n = 1;
+  for (int m = m0; m < m1; ++m) {
+    k.dims[m - m0] = Lt.n[m];
+    k.offs[m - m0] = Lt.off[m];
+    n *= Lt.n[m];
+  }
+  const int g = (int)std::max<i64>(1, std::min<i64>((n + 255) / 256, 4 * (i64)device_cus()));
+  hipLaunchKernelGGL((k_kron<Acc>), dim3(g), dim3(256), 0, c.s, (const double*)c.x, k, w, n, scale0,
+                     sdiv);
+  TVC_TRY_HIP(hipGetLastError());
+  return TVC_OK;
+}
+
+#define TVC_TRY(expr)                 \
+  do {                                \
+    tvc_status s_ = (expr);           \
+    if (s_ != TVC_OK) return s_;      \
+  } while (0)
+
+template <typename Acc>
+tvc_status sweep(const Ctx& c) {
+  const Layout& Lt = *c.Lt;
+  const tvc_tensor* A = c.A;
+  const int d = Lt.d;
+  const i64* n = Lt.n;
+  Acc* wv = c.at<Acc>(Lt.o_wv);
+  Acc* y = c.at<Acc>(Lt.o_y);
+  const bool f8 = A->dtype == TVC_F8E4M3;
+  if (d == 2) {
+    TVC_TRY(run(c, A->dtype, A->data, n[0], n[1], 1, wv + Lt.woff[1], y,
+                f8 ? A->slab_scale : nullptr, 1));
+    TVC_TRY(normalize<Acc>(c, y, 0));
+    const Acc* w0 = wv + Lt.woff[0];
+    if (f8) {
+      Acc* sw = c.at<Acc>(Lt.o_w2);
+      TVC_TRY(kron<Acc>(c, 0, 1, sw, A->slab_scale, 1));
+      w0 = sw;
+    }
+    TVC_TRY(run(c, A->dtype, A->data, 1, n[0], n[1], w0, y, nullptr, 1));
+    return normalize<Acc>(c, y, 1);
+  }
+  Acc* Mm = c.at<Acc>(Lt.o_M);
+  Acc* w2 = c.at<Acc>(Lt.o_w2);
+  Acc* Wa = c.at<Acc>(Lt.o_Wa);
+  Acc* Wb = c.at<Acc>(Lt.o_Wb);
+  Acc* Ca = c.at<Acc>(Lt.o_Ca);
+  Acc* Cb = c.at<Acc>(Lt.o_Cb);
+  // pass 1: M = A contracted over modes 2..d-1
+  const Acc* w1 = wv + Lt.woff[2];
+  if (d >= 4) {
+    Acc* w1b = c.at<Acc>(Lt.o_w1);
+    TVC_TRY(kron<Acc>(c, 2, d, w1b, nullptr, 1));
+    w1 = w1b;
+  }
+  TVC_TRY(run(c, A->dtype, A->data, Lt.n01, Lt.R1, 1, w1, Mm, f8 ? A->slab_scale : nullptr, n[1]));
+  // j = 0, 1
+  TVC_TRY(run(c, Lt.acc_dt, Mm, n[0], n[1], 1, wv + Lt.woff[1], y, nullptr, 1));
+  TVC_TRY(normalize<Acc>(c, y, 0));
+  TVC_TRY(run(c, Lt.acc_dt, Mm, 1, n[0], n[1], wv + Lt.woff[0], y, nullptr, 1));
+  TVC_TRY(normalize<Acc>(c, y, 1));
+  // pass 2: W_2 = A contracted with x_0 (x) x_1 (slab scale folded into the weights)
+  TVC_TRY(kron<Acc>(c, 0, 2, w2, f8 ? A->slab_scale : nullptr, n[1]));
+  TVC_TRY(run(c, A->dtype, A->data, 1, Lt.n01, Lt.R1, w2, Wa, nullptr, 1));
+  // j >= 2
+  Acc* Wcur = Wa;
+  Acc* Wother = Wb;
+  i64 wsize = Lt.R1;
+  for (int j = 2; j < d; ++j) {
+    if (j > 2) {
+      TVC_TRY(run(c, Lt.acc_dt, Wcur, 1, n[j - 1], wsize / n[j - 1], wv + Lt.woff[j - 1], Wother,
+                  nullptr, 1));
+      wsize /= n[j - 1];
+      std::swap(Wcur, Wother);
+    }
+    const Acc* src = Wcur;
+    i64 t = wsize;
+    Acc* bufs[2] = {Ca, Cb};
+    int bi = 0;
+    for (int m = d - 1; m > j; --m) {
+      Acc* dst = (m == j + 1) ? y : bufs[bi];
+      TVC_TRY(run(c, Lt.acc_dt, src, t / n[m], n[m], 1, wv + Lt.woff[m], dst, nullptr, 1));
+      t /= n[m];
+      src = dst;
+      bi ^= 1;
+    }
+    TVC_TRY(normalize<Acc>(c, src, j));
+  }
+  return TVC_OK;
+}
+
+template <typename Acc>
+tvc_status iterate(const Ctx& c, int sweeps) {
+  const Layout& Lt = *c.Lt;
+  const int g = (int)std::max<i64>(1, std::min<i64>((Lt.nsum + 255) / 256, 64));
+  VecOffsets vo;
+  vo.d = Lt.d;
+  for (int m = 0; m < Lt.d; ++m) {
+    vo.n[m] = Lt.n[m];
+    vo.off[m] = Lt.off[m];
+    vo.woff[m] = Lt.woff[m];
+  }
+  hipLaunchKernelGGL((k_prepare<Acc>), dim3(g), dim3(256), 0, c.s, (const double*)c.x,
+                     c.at<Acc>(Lt.o_wv), vo, c.st);
+  TVC_TRY_HIP(hipGetLastError());
+  for (int i = 0; i < sweeps; ++i) TVC_TRY(sweep<Acc>(c));
+  return TVC_OK;
+}
+
+tvc_status check_hopm_args(const tvc_tensor* A, double* x, void* ws, size_t ws_bytes,
+                           const Layout& Lt) {
+  TVC_TRY(check_tensor(A, "A"));
+  if (A->order < 2) return fail(TVC_EINVAL, "HOPM needs order >= 2");
+  if (!x) return fail(TVC_EINVAL, "x is NULL");
+  if ((uintptr_t)x % 8 != 0) return fail(TVC_EINVAL, "x not 8-byte aligned");
+  if (!ws || (uintptr_t)ws % 256 != 0 || ws_bytes < Lt.total)
+    return fail(TVC_EWORKSPACE, "HOPM workspace of " + std::to_string(Lt.total) +
+                                    " bytes (256-byte aligned) required");
+  const size_t abytes = (size_t)numel(A) * elem_bytes(A->dtype);
+  const size_t xbytes = (size_t)Lt.nsum * 8;
+  if (overlaps(x, xbytes, A->data, abytes) || overlaps(ws, ws_bytes, A->data, abytes) ||
+      overlaps(ws, ws_bytes, x, xbytes))
+    return fail(TVC_EALIAS, "x, workspace and A must not overlap");
+  return TVC_OK;
+}
+
+tvc_status iterate_any(const tvc_tensor* A, double* x, int sweeps, void* ws, size_t ws_bytes,
+                       hopm_stats* st, hipStream_t s) {
+  Layout Lt = make_layout(A);
+  TVC_TRY(check_hopm_args(A, x, ws, ws_bytes, Lt));
+  if (sweeps < 1) return fail(TVC_EINVAL, "sweeps must be >= 1");
+  if (!st) return fail(TVC_EINVAL, "stats pointer is NULL");
+  Ctx c{&Lt, A, x, (char*)ws, st, s};
+  if (A->dtype == TVC_F64) return iterate<double>(c, sweeps);
+  return iterate<float>(c, sweeps);
+}
+
+}  // namespace
+}  // namespace tvc
+
+using namespace tvc;
+
+extern "C" {
+
+size_t hopm_workspace_bytes(const tvc_tensor* A) {
+  if (check_tensor(A, "A") != TVC_OK || A->order < 2) return 0;
+  Layout Lt = make_layout(A);
+  if (A->dtype != TVC_F64 && A->dtype != TVC_F32) {
+    // the same workspace must also serve the float32 refinement tensor
+    tvc_tensor B = *A;
+    B.dtype = TVC_F32;
+    B.slab_scale = nullptr;
+    Layout Lb = make_layout(&B);
+    return std::max(Lt.total, Lb.total);
+  }
+  return Lt.total;
+}
+
+int32_t hopm_iterate(const tvc_tensor* A, double* x, int32_t sweeps, void* ws, size_t ws_bytes,
+                     hopm_stats* d_stats, void* stream) {
+  return iterate_any(A, x, sweeps, ws, ws_bytes, d_stats, (hipStream_t)stream);
+}
+
+int32_t hopm_solve(const tvc_tensor* A, const tvc_tensor* A_refine, double* x, double tol,
+                   int32_t max_sweeps, int32_t check_every, int32_t refine_sweeps, void* ws,
+                   size_t ws_bytes, hopm_stats* h_out, void* stream) {
+  TVC_TRY(check_tensor(A, "A"));
+  if (A->order < 2) return fail(TVC_EINVAL, "HOPM needs order >= 2");
+  if (!h_out) return fail(TVC_EINVAL, "h_out is NULL");
+  if (max_sweeps < 1 || check_every < 1) return fail(TVC_EINVAL, "max_sweeps and check_every must be >= 1");
+  if (!(tol >= 0.0)) return fail(TVC_EINVAL, "tol must be >= 0");
+  if (A_refine) {
+    TVC_TRY(check_tensor(A_refine, "A_refine"));
+    if (A_refine->dtype != TVC_F32) return fail(TVC_EDTYPE, "A_refine must be TVC_F32");
+    if (A_refine->order != A->order) return fail(TVC_EINVAL, "A_refine dims differ from A");
+    for (int i = 0; i < A->order; ++i)
+      if (A_refine->dims[i] != A->dims[i]) return fail(TVC_EINVAL, "A_refine dims differ from A");
+    if (refine_sweeps < 0) return fail(TVC_EINVAL, "refine_sweeps must be >= 0");
+  }
+  Layout Lt = make_layout(A);
+  if (ws_bytes < hopm_workspace_bytes(A))
+    return fail(TVC_EWORKSPACE, "HOPM workspace too small");
+  // device stats live in the first slot of the workspace
+  hopm_stats* dst = (hopm_stats*)((char*)ws + Lt.o_stats);
+  hipStream_t s = (hipStream_t)stream;
+  hopm_stats h{};
+  bool converged = false;
+  int done = 0;
+  while (done < max_sweeps) {
+    const int k = std::min(check_every, max_sweeps - done);
+    TVC_TRY(iterate_any(A, x, k, ws, ws_bytes, dst, s));
+    TVC_TRY_HIP(hipMemcpyAsync(&h, dst, sizeof(h), hipMemcpyDeviceToHost, s));
+    TVC_TRY_HIP(hipStreamSynchronize(s));
+    done += k;
+    if (h.status != TVC_OK) {
+      h.sweeps = done;
+      *h_out = h;
+      return fail(TVC_EDEGENERATE, "zero-norm vector during HOPM");
+    }
+    if (h.delta < tol) {
+      converged = true;
+      break;
+    }
+  }
+  h.sweeps = done;
+  int rdone = 0;
+  if (A_refine && refine_sweeps > 0) {
+    hopm_stats hr{};
+    while (rdone < refine_sweeps) {
+      const int k = std::min(check_every, refine_sweeps - rdone);
+      TVC_TRY(iterate_any(A_refine, x, k, ws, ws_bytes, dst, s));
+      TVC_TRY_HIP(hipMemcpyAsync(&hr, dst, sizeof(hr), hipMemcpyDeviceToHost, s));
+      TVC_TRY_HIP(hipStreamSynchronize(s));
+      rdone += k;
+      if (hr.status != TVC_OK) {
+        h.status = hr.status;
+        h.refine_sweeps = rdone;
+        *h_out = h;
+        return fail(TVC_EDEGENERATE, "zero-norm vector during refinement");
+      }
+      h.lambda = hr.lambda;
+      h.delta = hr.delta;
+      if (hr.delta < tol) break;
+    }
+  }
+  h.refine_sweeps = rdone;
+  *h_out = h;
+  if (!converged) return fail(TVC_ENOTCONVERGED, "max_sweeps reached");
+  return TVC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Internal host-side interfaces of libtvc (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/tvc.h"
+
+namespace tvc {
+
+typedef int64_t i64;
+
+// Launch roles: kernels launched for tvc_contract and for the HOPM sweep are
+// separate instantiations, so profiles attribute time to each.
+enum Role { kRoleContract = 0, kRoleHopm = 1 };
+
+// Kernel families for the (left, n_k, right) = (L, M, R) view of Sec. 3.
+enum Family { kRow = 0, kCol = 1, kSlab = 2 };
+
+// Launch parameters chosen by plan_tvc (or forced by tvc_set_tuning).
+struct TvcPlan {
+  int family = kRow;
+  bool vec = false;      // 16-byte units
+  bool lng = true;       // kRow: a wave per row (true) or several rows per wave
+  int glog = 0;          // log2 lanes per row (short rows / slabs)
+  int rb = 1;            // kRow long: rows sharing one weight load
+  int splitm = 1;        // kCol: wave groups splitting the contracted extent
+  int nsplit = 1;        // split of the contracted extent across tasks
+  i64 chunk = 0;         // units (kRow) or rows (kCol/kSlab) per split
+  i64 upr = 0;           // units per row
+  i64 tasks = 0;         // independent work items (waves or workgroups)
+  int grid = 1;          // workgroups launched
+  size_t part_bytes = 0; // partial-sum scratch (nsplit > 1)
+};
+
+struct Tuning {
+  int blocks_per_cu[3] = {0, 0, 0};
+  int split_m = 0;
+  int unroll = 0;
+};
+Tuning& tuning();
+
+// Elements' storage size, accumulation size.
+size_t elem_bytes(int dtype);
+size_t acc_bytes(int dtype);
+int device_cus();
+
+TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a16, bool w16);
+
+// y[l, r] = alpha * oscale[l / odiv] * sum_m A[l, m, r] * w[m] + beta * y[l, r]
+// w, y, part: accumulation type of `dtype` (double for TVC_F64, else float).
+// oscale may be NULL.  part: plan.part_bytes of scratch (may be NULL if 0).
+hipError_t run_tvc(int dtype, const void* A, i64 L, i64 M, i64 R, const void* w,
+                   void* y, double alpha, double beta, const float* oscale,
+                   i64 odiv, const TvcPlan& p, void* part, hipStream_t st,
+                   int role = kRoleContract);
+
+// Convenience: plan + run with a workspace (error if too small).
+tvc_status tvc_run_auto(int dtype, const void* A, i64 L, i64 M, i64 R,
+                        const void* w, void* y, double alpha, double beta,
+                        const float* oscale, i64 odiv, void* ws, size_t ws_bytes,
+                        hipStream_t st, int role = kRoleContract);
+
+// Round up to 256 bytes (workspace carving).
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Thread-local error message.
+void set_error(const std::string& msg);
+tvc_status fail(tvc_status s, const std::string& msg);
+
+// Validation shared by the entry points.
+tvc_status check_tensor(const tvc_tensor* A, const char* what);
+i64 numel(const tvc_tensor* A);
+void mode_view(const tvc_tensor* A, int mode, i64* L, i64* M, i64* R);
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes);
+
+}  // namespace tvc

@@ -1,0 +1,503 @@
+// Streaming kernels of the k-mode tensor-vector contraction on gfx950.
+//
+// Sec. 3 of the paper views A as the matrix A^{uv x n_k}; here the same view
+// is kept three-dimensional, A[L][M][R] with L = prod_{i<k} n_i, M = n_k,
+// R = prod_{i>k} n_i, and
+//     y[l, r] = sum_m A[l, m, r] * w[m].
+// The contraction reads every element once and does 2 flops per element, so
+// it is bound by HBM bandwidth.  Each layout gets its own coalesced access:
+//   kRow  (R == 1)          rows are contiguous: lanes stride along a row and
+//                           a wave reduction gives y[l]; short rows put
+//                           several rows in one wave with a segmented
+//                           reduction.  Long rows with few of them are split
+//                           along the row into chunks (partials + finalize).
+//   kCol  (R large)         lanes own 16-byte column groups of one slab and
+//                           stream down the M rows; wave groups of a
+//                           workgroup split M and combine in LDS.
+//   kSlab (R small)         one wave reads whole slabs [M][R] with lanes
+//                           covering (row, column-group) pairs, then reduces
+//                           across the lanes holding the same columns.
+// Splitting the contracted extent across tasks writes partial sums to a
+// workspace that k_finalize reduces in a fixed order, so results do not
+// depend on scheduling (no floating-point atomics).
+#include <algorithm>
+
+#include "common.h"
+#include "internal.h"
+
+namespace tvc {
+
+constexpr int kUnroll = 4;   // 16-byte loads a lane keeps in flight per row
+
+template <typename Acc>
+struct RowArgs {
+  const void* A; const Acc* w; Acc* y; Acc* part;
+  i64 L, upr, chunk;
+  int nsplit, glog;
+  Acc alpha, beta;
+  const float* oscale; i64 odiv;
+};
+
+template <typename Acc>
+struct ColArgs {
+  const void* A; const Acc* w; Acc* y; Acc* part;
+  i64 L, M, upr, R, ctiles, chunk;
+  int nsplit, glog;
+  Acc alpha, beta;
+  const float* oscale; i64 odiv;
+};
+
+template <typename Acc>
+__device__ __forceinline__ Acc epilogue(Acc v, const Acc* y, i64 idx, i64 l, Acc alpha,
+                                        Acc beta, const float* oscale, i64 odiv) {
+  if (oscale) v *= (Acc)oscale[l / odiv];
+  v *= alpha;
+  if (beta != (Acc)0) v += beta * y[idx];
+  return v;
+}
+
+// ---------------------------------------------------------------- kRow, long
+// One wave per (group of RB rows, chunk of the row).  Task t -> (chunk s,
+// row group g) with g fastest, so consecutive waves share a weight chunk.
+template <int DT, bool VEC, int RB, int ROLE>
+__global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Acc> a) {
+  typedef typename St<DT>::Acc Acc;
+  typedef Unit<DT, VEC> U;
+  constexpr int EU = U::EU;
+  const int lane = lane_id();
+  const i64 wave = (i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
+  const i64 nwaves = (i64)gridDim.x * (kBlock / kWave);
+  const i64 ngroups = (a.L + RB - 1) / RB;
+  const i64 ntasks = ngroups * a.nsplit;
+  for (i64 t = wave; t < ntasks; t += nwaves) {
+    const i64 s = t / ngroups;
+    const i64 row0 = (t - s * ngroups) * RB;
+    const i64 u0 = s * a.chunk;
+    const i64 u1 = min(a.upr, u0 + a.chunk);
+    Acc acc[RB][EU];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int e = 0; e < EU; ++e) acc[r][e] = (Acc)0;
+    for (i64 u = u0 + lane; u < u1; u += (i64)kWave * kUnroll) {
+      typename U::Raw raw[kUnroll][RB];
+      Acc wv[kUnroll][EU];
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) {
+        const i64 uk = u + (i64)k * kWave;
+        const bool ok = uk < u1;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const i64 row = row0 + r;
+          raw[k][r] = (ok && row < a.L) ? U::load(a.A, row * a.upr + uk) : U::zero();
+        }
+        if (ok) {
+          load_w<Acc, EU>(a.w, uk * EU, wv[k]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < EU; ++e) wv[k][e] = (Acc)0;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k)
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          Acc v[EU];
+          U::unpack(raw[k][r], v);
+#pragma unroll
+          for (int e = 0; e < EU; ++e) acc[r][e] = fma(v[e], wv[k][e], acc[r][e]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      Acc s_ = (Acc)0;
+#pragma unroll
+      for (int e = 0; e < EU; ++e) s_ += acc[r][e];
+      s_ = wave_sum(s_);
+      const i64 row = row0 + r;
+      if (lane == 0 && row < a.L) {
+        if (a.nsplit > 1) a.part[s * a.L + row] = s_;
+        else a.y[row] = epilogue(s_, a.y, row, row, a.alpha, a.beta, a.oscale, a.odiv);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- kRow, short
+// G = 2^glog lanes per row (G >= units per row), 64/G rows per wave load.
+template <int DT, bool VEC, int ROLE>
+__global__ __launch_bounds__(kBlock) void k_row_short(RowArgs<typename St<DT>::Acc> a) {
+  typedef typename St<DT>::Acc Acc;
+  typedef Unit<DT, VEC> U;
+  constexpr int EU = U::EU;
+  const int lane = lane_id();
+  const int G = 1 << a.glog;
+  const int P = kWave >> a.glog;
+  const int sub = lane & (G - 1);
+  const int rsub = lane >> a.glog;
+  const bool active = sub < a.upr;
+  Acc wv[EU];
+  if (active) {
+    load_w<Acc, EU>(a.w, (i64)sub * EU, wv);
+  } else {
+#pragma unroll
+    for (int e = 0; e < EU; ++e) wv[e] = (Acc)0;
+  }
+  const i64 wave = (i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
+  const i64 nwaves = (i64)gridDim.x * (kBlock / kWave);
+  const i64 per = (i64)P * kUnroll;
+  for (i64 base = wave * per; base < a.L; base += nwaves * per) {
+    typename U::Raw raw[kUnroll];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+      const i64 row = base + (i64)k * P + rsub;
+      raw[k] = (active && row < a.L) ? U::load(a.A, row * a.upr + sub) : U::zero();
+    }
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+      Acc v[EU];
+      U::unpack(raw[k], v);
+      Acc s_ = (Acc)0;
+#pragma unroll
+      for (int e = 0; e < EU; ++e) s_ = fma(v[e], wv[e], s_);
+      for (int off = G >> 1; off >= 1; off >>= 1) s_ += shfl_xor(s_, off);
+      const i64 row = base + (i64)k * P + rsub;
+      if (sub == 0 && row < a.L)
+        a.y[row] = epilogue(s_, a.y, row, row, a.alpha, a.beta, a.oscale, a.odiv);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- kCol
+// Workgroup task = (split s, slab l, column tile ct), ct fastest.  TC threads
+// along columns (one unit each), SPLITM wave groups along the rows.
+template <int DT, bool VEC, int SPLITM, int ROLE>
+__global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a) {
+  typedef typename St<DT>::Acc Acc;
+  typedef Unit<DT, VEC> U;
+  constexpr int EU = U::EU;
+  constexpr int TC = kBlock / SPLITM;
+  __shared__ Acc red[SPLITM > 1 ? (SPLITM - 1) * TC * EU : 1];
+  const int tc = threadIdx.x % TC;
+  const int grp = threadIdx.x / TC;
+  const i64 ntasks = a.L * a.ctiles * a.nsplit;
+  for (i64 t = blockIdx.x; t < ntasks; t += gridDim.x) {
+    const i64 ct = t % a.ctiles;
+    const i64 rest = t / a.ctiles;
+    const i64 l = rest % a.L;
+    const i64 s = rest / a.L;
+    const i64 c = ct * TC + tc;
+    const bool active = c < a.upr;
+    const i64 m0 = s * a.chunk;
+    const i64 m1 = min(a.M, m0 + a.chunk);
+    const i64 slab = l * a.M;
+    Acc acc[EU];
+#pragma unroll
+    for (int e = 0; e < EU; ++e) acc[e] = (Acc)0;
+    for (i64 m = m0 + grp; m < m1; m += (i64)SPLITM * kUnroll) {
+      typename U::Raw raw[kUnroll];
+      Acc wv[kUnroll];
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) {
+        const i64 mk = m + (i64)k * SPLITM;
+        const bool ok = mk < m1;
+        raw[k] = (active && ok) ? U::load(a.A, (slab + mk) * a.upr + c) : U::zero();
+        wv[k] = ok ? a.w[mk] : (Acc)0;
+      }
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) {
+        Acc v[EU];
+        U::unpack(raw[k], v);
+#pragma unroll
+        for (int e = 0; e < EU; ++e) acc[e] = fma(v[e], wv[k], acc[e]);
+      }
+    }
+    if constexpr (SPLITM > 1) {
+      if (grp > 0) {
+#pragma unroll
+        for (int e = 0; e < EU; ++e) red[((grp - 1) * TC + tc) * EU + e] = acc[e];
+      }
+      __syncthreads();
+      if (grp == 0) {
+#pragma unroll
+        for (int g = 1; g < SPLITM; ++g)
+#pragma unroll
+          for (int e = 0; e < EU; ++e) acc[e] += red[((g - 1) * TC + tc) * EU + e];
+      }
+    }
+    if (grp == 0 && active) {
+#pragma unroll
+      for (int e = 0; e < EU; ++e) {
+        const i64 idx = l * a.R + c * EU + e;
+        if (a.nsplit > 1) a.part[s * (a.L * a.R) + idx] = acc[e];
+        else a.y[idx] = epilogue(acc[e], a.y, idx, l, a.alpha, a.beta, a.oscale, a.odiv);
+      }
+    }
+    if constexpr (SPLITM > 1) __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- kSlab
+// Wave task = (split s, slab l).  G = 2^glog lanes per row, P = 64/G rows
+// per wave load; lanes with equal (lane mod G) hold the same columns.
+template <int DT, bool VEC, int ROLE>
+__global__ __launch_bounds__(kBlock) void k_slab(ColArgs<typename St<DT>::Acc> a) {
+  typedef typename St<DT>::Acc Acc;
+  typedef Unit<DT, VEC> U;
+  constexpr int EU = U::EU;
+  const int lane = lane_id();
+  const int G = 1 << a.glog;
+  const int P = kWave >> a.glog;
+  const int sub = lane & (G - 1);
+  const int rsub = lane >> a.glog;
+  const bool active = sub < a.upr;
+  const i64 wave = (i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
+  const i64 nwaves = (i64)gridDim.x * (kBlock / kWave);
+  const i64 ntasks = a.L * a.nsplit;
+  for (i64 t = wave; t < ntasks; t += nwaves) {
+    const i64 l = t % a.L;
+    const i64 s = t / a.L;
+    const i64 m0 = s * a.chunk;
+    const i64 m1 = min(a.M, m0 + a.chunk);
+    const i64 slab = l * a.M;
+    Acc acc[EU];
+#pragma unroll
+    for (int e = 0; e < EU; ++e) acc[e] = (Acc)0;
+    for (i64 mb = m0; mb < m1; mb += (i64)P * kUnroll) {
+      typename U::Raw raw[kUnroll];
+      Acc wv[kUnroll];
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) {
+        const i64 mk = mb + (i64)k * P + rsub;
+        const bool ok = active && mk < m1;
+        raw[k] = ok ? U::load(a.A, (slab + mk) * a.upr + sub) : U::zero();
+        wv[k] = ok ? a.w[mk] : (Acc)0;
+      }
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) {
+        Acc v[EU];
+        U::unpack(raw[k], v);
+#pragma unroll
+        for (int e = 0; e < EU; ++e) acc[e] = fma(v[e], wv[k], acc[e]);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EU; ++e)
+      for (int off = G; off < kWave; off <<= 1) acc[e] += shfl_xor(acc[e], off);
+    if (rsub == 0 && active) {
+#pragma unroll
+      for (int e = 0; e < EU; ++e) {
+        const i64 idx = l * a.R + (i64)sub * EU + e;
+        if (a.nsplit > 1) a.part[s * (a.L * a.R) + idx] = acc[e];
+        else a.y[idx] = epilogue(acc[e], a.y, idx, l, a.alpha, a.beta, a.oscale, a.odiv);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- finalize
+// y[i] = epilogue(sum_{s < nsplit} part[s * n + i]) in split order.
+template <typename Acc, int ROLE>
+__global__ __launch_bounds__(kBlock) void k_finalize(const Acc* part, Acc* y, i64 n, int nsplit,
+                                                     i64 R, Acc alpha, Acc beta,
+                                                     const float* oscale, i64 odiv) {
+  for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (i64)gridDim.x * blockDim.x) {
+    Acc s = (Acc)0;
+    for (int k = 0; k < nsplit; ++k) s += part[(i64)k * n + i];
+    y[i] = epilogue(s, y, i, i / R, alpha, beta, oscale, odiv);
+  }
+}
+
+// ====================================================================== host
+namespace {
+
+int ceil_log2(i64 v) {
+  int g = 0;
+  while (((i64)1 << g) < v) ++g;
+  return g;
+}
+
+i64 cdiv(i64 a, i64 b) { return (a + b - 1) / b; }
+
+int grid_for(i64 blocks_needed, int family, int default_bpc) {
+  int bpc = tuning().blocks_per_cu[family] > 0 ? tuning().blocks_per_cu[family] : default_bpc;
+  i64 cap = (i64)bpc * device_cus();
+  return (int)std::max<i64>(1, std::min<i64>(blocks_needed, cap));
+}
+
+}  // namespace
+
+TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a16, bool w16) {
+  TvcPlan p;
+  const i64 b = (i64)elem_bytes(dtype);
+  const i64 epv = 16 / b;
+  const size_t ab = acc_bytes(dtype);
+  const int waves_per_block = kBlock / kWave;
+  if (R == 1) {
+    p.family = kRow;
+    p.vec = a16 && w16 && (M * b) % 16 == 0;
+    const i64 eu = p.vec ? epv : 1;
+    p.upr = M / eu;
+    if (p.upr > 32) {
+      p.lng = true;
+      p.rb = L >= 2 ? 2 : 1;
+      const i64 groups = cdiv(L, p.rb);
+      p.nsplit = 1;
+      p.chunk = p.upr;
+      // Few long rows: split each row so that enough waves stream at once.
+      const i64 want = 8 * (i64)device_cus();
+      if (groups < want && p.upr >= 2 * kWave * kUnroll) {
+        i64 ns = std::min<i64>(cdiv(2 * want, groups), p.upr / (kWave * kUnroll));
+        ns = std::max<i64>(ns, 1);
+        i64 chunk = cdiv(p.upr, ns);
+        chunk = cdiv(chunk, kWave) * kWave;
+        p.chunk = chunk;
+        p.nsplit = (int)cdiv(p.upr, chunk);
+      }
+      p.tasks = groups * p.nsplit;
+      p.grid = grid_for(cdiv(p.tasks, waves_per_block), kRow, 8);
+    } else {
+      p.lng = false;
+      p.glog = ceil_log2(std::max<i64>(p.upr, 1));
+      const i64 per = (i64)(kWave >> p.glog) * kUnroll;
+      p.tasks = cdiv(L, per);
+      p.grid = grid_for(cdiv(p.tasks, waves_per_block), kRow, 8);
+    }
+  } else {
+    p.vec = a16 && (R * b) % 16 == 0;
+    const i64 eu = p.vec ? epv : 1;
+    p.upr = R / eu;
+    if (p.upr > 32) {
+      p.family = kCol;
+      int sm = tuning().split_m > 0 ? tuning().split_m : (M >= 8 ? 4 : 1);
+      if (sm != 1 && sm != 2 && sm != 4) sm = 4;
+      p.splitm = sm;
+      const i64 tc = kBlock / sm;
+      const i64 ctiles = cdiv(p.upr, tc);
+      const i64 tasks = L * ctiles;
+      p.nsplit = 1;
+      p.chunk = M;
+      const i64 want = 4 * (i64)device_cus();
+      if (tasks < want && M >= (i64)sm * kUnroll * 8) {
+        i64 ns = std::min<i64>(cdiv(2 * want, tasks), M / ((i64)sm * kUnroll * 4));
+        ns = std::max<i64>(ns, 1);
+        p.chunk = cdiv(M, ns);
+        p.nsplit = (int)cdiv(M, p.chunk);
+      }
+      p.tasks = tasks * p.nsplit;
+      p.grid = grid_for(p.tasks, kCol, 8);
+    } else {
+      p.family = kSlab;
+      p.glog = ceil_log2(std::max<i64>(p.upr, 1));
+      const i64 P = kWave >> p.glog;
+      p.nsplit = 1;
+      p.chunk = M;
+      const i64 want = 16 * (i64)device_cus();
+      if (L < want && M >= P * kUnroll * 8) {
+        i64 ns = std::min<i64>(cdiv(2 * want, L), M / (P * kUnroll * 4));
+        ns = std::max<i64>(ns, 1);
+        p.chunk = cdiv(M, ns);
+        p.nsplit = (int)cdiv(M, p.chunk);
+      }
+      p.tasks = L * p.nsplit;
+      p.grid = grid_for(cdiv(p.tasks, waves_per_block), kSlab, 8);
+    }
+  }
+  p.part_bytes = p.nsplit > 1 ? align256((size_t)p.nsplit * (size_t)(L * R) * ab) : 0;
+  return p;
+}
+
+namespace {
+
+template <int DT, int ROLE>
+hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, double alpha,
+                  double beta, const float* oscale, i64 odiv, const TvcPlan& p, void* part_,
+                  hipStream_t st) {
+  typedef typename St<DT>::Acc Acc;
+  const Acc* w = (const Acc*)w_;
+  Acc* y = (Acc*)y_;
+  Acc* part = (Acc*)part_;
+  const dim3 blk(kBlock);
+  const dim3 grd(p.grid);
+  if (p.family == kRow) {
+    RowArgs<Acc> a{A, w, y, part, L, p.upr, p.chunk, p.nsplit, p.glog, (Acc)alpha, (Acc)beta,
+                   oscale, odiv};
+    if (p.lng) {
+      if (p.vec) {
+        if (p.rb == 2) hipLaunchKernelGGL((k_row_long<DT, true, 2, ROLE>), grd, blk, 0, st, a);
+        else hipLaunchKernelGGL((k_row_long<DT, true, 1, ROLE>), grd, blk, 0, st, a);
+      } else {
+        if (p.rb == 2) hipLaunchKernelGGL((k_row_long<DT, false, 2, ROLE>), grd, blk, 0, st, a);
+        else hipLaunchKernelGGL((k_row_long<DT, false, 1, ROLE>), grd, blk, 0, st, a);
+      }
+    } else {
+      if (p.vec) hipLaunchKernelGGL((k_row_short<DT, true, ROLE>), grd, blk, 0, st, a);
+      else hipLaunchKernelGGL((k_row_short<DT, false, ROLE>), grd, blk, 0, st, a);
+    }
+  } else {
+    const i64 tc = kBlock / p.splitm;
+    ColArgs<Acc> a{A, w, y, part, L, M, p.upr, R, (p.upr + tc - 1) / tc, p.chunk, p.nsplit,
+                   p.glog, (Acc)alpha, (Acc)beta, oscale, odiv};
+    if (p.family == kCol) {
+      if (p.vec) {
+        if (p.splitm == 4) hipLaunchKernelGGL((k_col<DT, true, 4, ROLE>), grd, blk, 0, st, a);
+        else if (p.splitm == 2) hipLaunchKernelGGL((k_col<DT, true, 2, ROLE>), grd, blk, 0, st, a);
+        else hipLaunchKernelGGL((k_col<DT, true, 1, ROLE>), grd, blk, 0, st, a);
+      } else {
+        if (p.splitm == 4) hipLaunchKernelGGL((k_col<DT, false, 4, ROLE>), grd, blk, 0, st, a);
+        else if (p.splitm == 2) hipLaunchKernelGGL((k_col<DT, false, 2, ROLE>), grd, blk, 0, st, a);
+        else hipLaunchKernelGGL((k_col<DT, false, 1, ROLE>), grd, blk, 0, st, a);
+      }
+    } else {
+      if (p.vec) hipLaunchKernelGGL((k_slab<DT, true, ROLE>), grd, blk, 0, st, a);
+      else hipLaunchKernelGGL((k_slab<DT, false, ROLE>), grd, blk, 0, st, a);
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (p.nsplit > 1) {
+    const i64 n = L * R;
+    const int g = (int)std::max<i64>(1, std::min<i64>(cdiv(n, kBlock), 4 * (i64)device_cus()));
+    hipLaunchKernelGGL((k_finalize<Acc, ROLE>), dim3(g), blk, 0, st, (const Acc*)part, y, n, p.nsplit,
+                       R, (Acc)alpha, (Acc)beta, oscale, odiv);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace
+
+hipError_t run_tvc(int dtype, const void* A, i64 L, i64 M, i64 R, const void* w, void* y,
+                   double alpha, double beta, const float* oscale, i64 odiv, const TvcPlan& p,
+                   void* part, hipStream_t st, int role) {
+#define TVC_RUN(D)                                                                               \
+  return role == kRoleHopm                                                                       \
+             ? run_dt<D, kRoleHopm>(A, L, M, R, w, y, alpha, beta, oscale, odiv, p, part, st)   \
+             : run_dt<D, kRoleContract>(A, L, M, R, w, y, alpha, beta, oscale, odiv, p, part, st)
+  switch (dtype) {
+    case TVC_F64: TVC_RUN(TVC_F64);
+    case TVC_F32: TVC_RUN(TVC_F32);
+    case TVC_F16: TVC_RUN(TVC_F16);
+    case TVC_BF16: TVC_RUN(TVC_BF16);
+    case TVC_F8E4M3: TVC_RUN(TVC_F8E4M3);
+    default: return hipErrorInvalidValue;
+  }
+#undef TVC_RUN
+}
+
+tvc_status tvc_run_auto(int dtype, const void* A, i64 L, i64 M, i64 R, const void* w, void* y,
+                        double alpha, double beta, const float* oscale, i64 odiv, void* ws,
+                        size_t ws_bytes, hipStream_t st, int role) {
+  const bool a16 = ((uintptr_t)A % 16) == 0;
+  const bool w16 = ((uintptr_t)w % 16) == 0;
+  TvcPlan p = plan_tvc(dtype, L, M, R, a16, w16);
+  if (p.part_bytes > ws_bytes || (p.part_bytes > 0 && ws == nullptr))
+    return fail(TVC_EWORKSPACE, "internal contraction needs " + std::to_string(p.part_bytes) +
+                                    " workspace bytes");
+  hipError_t e = run_tvc(dtype, A, L, M, R, w, y, alpha, beta, oscale, odiv, p, ws, st, role);
+  if (e != hipSuccess) return fail(TVC_EHIP, std::string("launch failed: ") + hipGetErrorString(e));
+  return TVC_OK;
+}
+
+}  // namespace tvc

@@ -1,0 +1,106 @@
+"""The C ABI: the shared library loads, exports every function include/tvc.h
+declares, and rejects bad arguments on the host before any device work.
+CPU only (no kernel is launched)."""
+import ctypes
+import re
+from pathlib import Path
+
+import pytest
+
+from paper_2501_03121_amd import _lib as L
+
+HEADER = Path(__file__).resolve().parents[1] / "include" / "tvc.h"
+
+
+def declared_functions():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("defined",)))
+
+
+def test_header_declares_core_calls():
+    names = declared_functions()
+    for n in ("tvc_contract", "hopm_iterate", "hopm_solve", "tvc_contract_workspace_bytes",
+              "hopm_workspace_bytes", "tvc_status_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_signatures_cover_header():
+    assert set(declared_functions()) <= set(L.SIGNATURES)
+
+
+def test_status_strings():
+    lib = L.lib()
+    for code, name in L.STATUS_NAMES.items():
+        assert lib.tvc_status_string(code).decode() == name
+    assert lib.tvc_version() >= 100
+
+
+def tensor(dims, dtype=L.TVC_F32, data=4096, scale=None):
+    return L.make_tensor(len(dims), dims, dtype, data, scale)
+
+
+def test_contract_argument_errors():
+    lib = L.lib()
+    ok = tensor((4, 5, 6))
+    x, y = 1 << 20, 2 << 20
+    cases = [
+        (tensor((4, 5, 6), data=0), 0, x, y, L.TVC_EINVAL),          # NULL data
+        (tensor((4, 0, 6)), 0, x, y, L.TVC_EINVAL),                  # zero dim
+        (tensor((4, 5, 6), data=4098), 0, x, y, L.TVC_EINVAL),       # misaligned
+        (ok, 3, x, y, L.TVC_EINVAL),                                  # bad mode
+        (ok, -1, x, y, L.TVC_EINVAL),
+        (ok, 0, 0, y, L.TVC_EINVAL),                                  # NULL x
+        (ok, 0, x, 4096 + 8, L.TVC_EALIAS),                           # y inside A
+        (tensor((4, 5, 6), dtype=9), 0, x, y, L.TVC_EDTYPE),
+        (tensor((4, 5, 6), dtype=L.TVC_F8E4M3), 1, x, y, L.TVC_EDTYPE),   # no scales
+    ]
+    for t, mode, xp, yp, want in cases:
+        got = lib.tvc_contract(t, mode, xp, yp, 1.0, 0.0, None, 0, None)
+        assert got == want, (mode, got, want, lib.tvc_last_error())
+        assert lib.tvc_last_error()
+    bad = L.make_tensor(17, (1,) * 16, L.TVC_F32, 4096)
+    assert lib.tvc_contract(bad, 0, x, y, 1.0, 0.0, None, 0, None) == L.TVC_EINVAL
+
+
+def test_hopm_argument_errors():
+    lib = L.lib()
+    st = L.HopmStats()
+    one = tensor((7,))
+    assert lib.hopm_iterate(one, 1 << 20, 1, 1 << 24, 1 << 20, 1 << 22, None) == L.TVC_EINVAL
+    t = tensor((4, 5, 6))
+    need = lib.hopm_workspace_bytes(t)
+    assert need > 0
+    assert lib.hopm_iterate(t, 1 << 20, 1, None, 0, 1 << 22, None) == L.TVC_EWORKSPACE
+    assert lib.hopm_iterate(t, 1 << 20, 1, 1 << 24, need - 1, 1 << 22, None) == L.TVC_EWORKSPACE
+    assert lib.hopm_iterate(t, 1 << 20, 0, 1 << 24, need, 1 << 22, None) == L.TVC_EINVAL
+    # x overlapping A
+    assert lib.hopm_iterate(t, 4096, 1, 1 << 24, need, 1 << 22, None) == L.TVC_EALIAS
+    assert lib.hopm_solve(t, None, 1 << 20, 1e-6, 0, 1, 0, 1 << 24, need, st, None) == L.TVC_EINVAL
+    r = tensor((4, 5, 7))
+    assert lib.hopm_solve(t, r, 1 << 20, 1e-6, 5, 1, 1, 1 << 24, need, st, None) == L.TVC_EINVAL
+
+
+def test_quantize_argument_errors():
+    lib = L.lib()
+    t = tensor((4, 5))
+    assert lib.tvc_quantize(t, 1 << 20, L.TVC_F32, None, 0, None) == L.TVC_EDTYPE
+    assert lib.tvc_quantize(tensor((4, 5), dtype=L.TVC_F16), 1 << 20, L.TVC_BF16, None, 0, None) == L.TVC_EDTYPE
+    assert lib.tvc_quantize(t, 4096 + 16, L.TVC_BF16, None, 0, None) == L.TVC_EALIAS
+    assert lib.tvc_quantize(t, 1 << 20, L.TVC_F8E4M3, None, 0, None) == L.TVC_EINVAL
+
+
+def test_workspace_sizes_are_aligned_and_monotone():
+    lib = L.lib()
+    small = lib.hopm_workspace_bytes(tensor((16, 16, 16)))
+    big = lib.hopm_workspace_bytes(tensor((64, 64, 64)))
+    assert small % 256 == 0 and big % 256 == 0 and big > small
+    assert lib.tvc_contract_workspace_bytes(tensor((1 << 20,)), 0) > 0   # long single row splits
+    assert lib.tvc_contract_workspace_bytes(tensor((64, 64, 64)), 1) == 0

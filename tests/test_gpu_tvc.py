@@ -1,0 +1,118 @@
+"""Parity of the HIP contraction (tvc_contract through the C ABI) with the
+float64 oracle, for every mode, several orders and shapes that span many
+tiles with ragged tails, and every storage format."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2501_03121_amd as tvc
+from oracle import tvc as O
+from paper_2501_03121_amd import synth
+from _util import TOL, host, stored_tensor, vec
+
+pytestmark = pytest.mark.gpu
+
+FMTS = ["f64", "f32", "f16", "bf16", "e4m3"]
+SHAPES = [
+    (1000003,),            # one long row: split across workgroups
+    (33, 1029),            # rows not a multiple of 16 bytes
+    (64, 64, 64),
+    (7, 13, 5),
+    (3, 1, 4, 9),
+    (31, 33, 35),
+    (128, 96, 80),
+    (2, 3, 4, 5, 6, 7),
+    (17, 19, 23, 3),
+    (8, 4096, 2),          # many rows of a narrow slab
+    (3, 50000, 4),         # few slabs, long contracted extent
+    (5, 2, 70001),         # few wide rows
+    (2, 16, 16, 16, 2, 16),
+]
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("dims", SHAPES, ids=lambda d: "x".join(map(str, d)))
+def test_parity_all_modes(dev, fmt, dims):
+    A, S, exact = stored_tensor(dims, fmt, 1, dev)
+    for k in range(len(dims)):
+        x, xh = vec(dims[k], 10 + k, fmt, dev)
+        y = tvc.contract(A, x, k, scale=S)
+        torch.cuda.synchronize()
+        ref = O.tvc(exact, xh, k)
+        err = O.rel_err(host(y), ref)
+        assert y.shape == ref.shape
+        assert err <= TOL[fmt], (fmt, dims, k, err)
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32", "f16", "bf16"])
+def test_integer_inputs_bitwise(dev, fmt):
+    dims = (9, 40, 33, 5)
+    base = synth.integers(dims, 3, -8, 8)
+    dt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[fmt]
+    A = torch.from_numpy(base).to(dt).to(dev)
+    acc = torch.float64 if fmt == "f64" else torch.float32
+    for k, n in enumerate(dims):
+        xh = synth.integers(n, 4 + k, -4, 4)
+        y = tvc.contract(A, torch.from_numpy(xh).to(acc).to(dev), k)
+        assert np.array_equal(host(y), O.tvc(base, xh, k)), (fmt, k)
+
+
+def test_e4m3_integer_codes_bitwise(dev):
+    dims = (6, 20, 17)
+    base = synth.integers(dims, 5, -16, 16)
+    from oracle import quant as Q
+    codes = Q.e4m3_from_f32(base.astype(np.float32))
+    A = torch.from_numpy(codes).view(torch.float8_e4m3fn).to(dev)
+    S = torch.ones(dims[0], dtype=torch.float32, device=dev)
+    for k, n in enumerate(dims):
+        xh = synth.integers(n, 6 + k, -3, 3)
+        y = tvc.contract(A, torch.from_numpy(xh).float().to(dev), k, scale=S)
+        assert np.array_equal(host(y), O.tvc(base, xh, k))
+
+
+def test_one_hot_is_slice(dev):
+    dims = (5, 130, 7, 9)
+    A, _, exact = stored_tensor(dims, "f32", 7, dev)
+    for k, n in enumerate(dims):
+        for m in (0, n // 2, n - 1):
+            e = torch.zeros(n, dtype=torch.float32, device=dev)
+            e[m] = 1.0
+            y = tvc.contract(A, e, k)
+            assert np.array_equal(host(y), np.take(exact, m, axis=k))
+
+
+def test_alpha_beta_and_nan_safety(dev):
+    dims = (12, 300, 11)
+    A, _, exact = stored_tensor(dims, "f64", 8, dev)
+    for k, n in enumerate(dims):
+        x, xh = vec(n, 20 + k, "f64", dev)
+        odims = O.output_dims(dims, k)
+        out = torch.full(odims, float("nan"), dtype=torch.float64, device=dev)
+        tvc.contract(A, x, k, alpha=2.5, beta=0.0, out=out)
+        assert torch.isfinite(out).all()
+        assert O.rel_err(host(out), 2.5 * O.tvc(exact, xh, k)) < 1e-12
+        y0 = synth.uniform(odims, 30 + k)
+        out = torch.from_numpy(y0).to(dev)
+        tvc.contract(A, x, k, alpha=-0.75, beta=1.5, out=out)
+        assert O.rel_err(host(out), O.tvc(exact, xh, k, alpha=-0.75, beta=1.5, y=y0)) < 1e-12
+
+
+@pytest.mark.parametrize("dims", [(1000003,), (3, 50000, 4), (256, 256, 256)])
+def test_bitwise_deterministic(dev, dims):
+    A, _, _ = stored_tensor(dims, "f32", 9, dev)
+    for k, n in enumerate(dims):
+        x, _ = vec(n, 40, "f32", dev)
+        a = tvc.contract(A, x, k).clone()
+        b = tvc.contract(A, x, k)
+        assert torch.equal(a, b)
+
+
+def test_misaligned_vector_falls_back(dev):
+    dims = (40, 256)
+    A, _, exact = stored_tensor(dims, "f32", 11, dev)
+    big = torch.zeros(257, dtype=torch.float32, device=dev)
+    xh = synth.uniform(256, 12)
+    big[1:] = torch.from_numpy(xh).float()
+    x = big[1:]          # 4-byte aligned, not 16
+    y = tvc.contract(A, x, 1)
+    assert O.rel_err(host(y), O.tvc(exact, xh.astype(np.float32), 1)) < 1e-5
