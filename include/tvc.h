@@ -176,6 +176,71 @@ int32_t tvc_quantize(const tvc_tensor* src, void* dst, int32_t dst_dtype,
                      float* slab_scale_out, int32_t flags, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Derivatives of Y = A x_k x (Sec. 3 definition) for an incoming gradient g
+ * of Y (N / n_k elements in the layout of y):
+ *   dx[m] = sum of A[.., m, ..] * g[..] over every other index
+ *           (A contracted with g over every mode except k), n_k elements;
+ *   dA    = alpha * (g outer x placed at mode k) + beta * dA, N elements
+ *           (beta == 0: dA is not read).
+ * tvc_backward_x: A of any dtype; g and dx are double for TVC_F64, float
+ * otherwise; one pass over A.  ws: tvc_backward_x_workspace_bytes(A, mode)
+ * bytes, 256-byte aligned (NULL when 0).
+ * tvc_backward_A: `dtype` (TVC_F32 or TVC_F64) is the type of g, x and dA.
+ * Errors: EINVAL, EDTYPE, EALIAS, EWORKSPACE, EHIP.
+ * ------------------------------------------------------------------------- */
+size_t tvc_backward_x_workspace_bytes(const tvc_tensor* A, int32_t mode);
+int32_t tvc_backward_x(const tvc_tensor* A, int32_t mode, const void* g, void* dx,
+                       void* ws, size_t ws_bytes, void* stream);
+int32_t tvc_backward_A(int32_t order, const int64_t* dims, int32_t dtype,
+                       int32_t mode, const void* g, const void* x, void* dA,
+                       double alpha, double beta, void* stream);
+
+/* Leave-one-out contractions (the operands of the HOPM update of Sec. 3, and
+ * of its derivative): with vectors v_0..v_{d-1} (device double, back to back
+ * as in hopm_iterate) it writes, for every mode m in the bit set `modes`,
+ *   out_m = A contracted with v_k over every k != m
+ * into out (device double, back to back; entries of other modes untouched).
+ * At most two passes over A.  ws: hopm_workspace_bytes(A) bytes. */
+int32_t tvc_leave_one_out(const tvc_tensor* A, const double* v, uint32_t modes,
+                          double* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Dense rank-R update: D := alpha * A + sum_r c_r f_{r,0} o ... o f_{r,d-1}
+ * over tensors of dims `dims` whose elements are `dtype` (TVC_F32 or
+ * TVC_F64); A may equal D, and may be NULL when alpha == 0.  factors: device
+ * double, R blocks of sum(dims) values (the factor vectors of term r back to
+ * back); coef: device double, R values.  R <= 4096.
+ * ws: tvc_rank_update_workspace_bytes(order, dims, R) bytes. */
+size_t tvc_rank_update_workspace_bytes(int32_t order, const int64_t* dims, int32_t R);
+int32_t tvc_rank_update(int32_t order, const int64_t* dims, int32_t dtype, const void* A,
+                        double alpha, int32_t R, const double* factors,
+                        const double* coef, void* D, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* hopm_iterate that also stores the pre-normalisation norm ||y|| of every
+ * (sweep, j) step: d_norms (device double) receives sweeps * order values,
+ * step (i, j) at i * order + j. */
+int32_t hopm_iterate_record(const tvc_tensor* A, double* x, int32_t sweeps, void* ws,
+                            size_t ws_bytes, hopm_stats* d_stats, double* d_norms,
+                            void* stream);
+
+/* Reverse pass through K HOPM sweeps (the derivative of unrolled HOPM).
+ * xs: device double, (K + 1) blocks of sum(dims) values: the vectors before
+ * sweep 0 and after every sweep (the checkpoints; the state before any step
+ * (i, j) is rebuilt from blocks i and i + 1).  norms: the K * order values
+ * of hopm_iterate_record.  gx: adjoint of the final vectors (sum(dims)
+ * doubles, or NULL for zero); glam: adjoint of the final lambda.
+ * Outputs (either may be NULL, not both): dA (N values, double for TVC_F64,
+ * float otherwise) := gA_scale * A + the gradient with respect to A, formed
+ * as K * order rank-1 terms and written once; dx0 (double, sum(dims)): the
+ * gradient with respect to the initial vectors.  Each step costs one
+ * leave-one-out call (two passes over A).  gA_scale != 0 needs a TVC_F32 or
+ * TVC_F64 tensor.  ws: hopm_backward_workspace_bytes(A, K) bytes. */
+size_t hopm_backward_workspace_bytes(const tvc_tensor* A, int32_t sweeps);
+int32_t hopm_backward(const tvc_tensor* A, const double* xs, const double* norms,
+                      int32_t sweeps, const double* gx, double glam, double gA_scale,
+                      void* dA, double* dx0, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Bandwidth probes (the analogue of the paper's STREAM yardstick, Sec. 5.1,
  * written for this library): read `bytes` bytes of src and write one float
  * per workgroup to sink (>= grid floats), or copy `bytes` bytes from src to

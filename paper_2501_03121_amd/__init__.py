@@ -12,7 +12,8 @@ from importlib import import_module
 _CORE = {
     "contract", "contract_plan", "hopm_iterate", "hopm_solve", "hopm_workspace", "read_stats",
     "quantize", "probe_read", "probe_copy", "pack_vectors", "unpack_vectors", "describe",
-    "HopmResult",
+    "HopmResult", "backward_x", "backward_A", "leave_one_out", "rank_update",
+    "hopm_iterate_record", "hopm_backward", "quantize",
 }
 
 

@@ -78,6 +78,21 @@ SIGNATURES = {
     "hopm_solve": (c_int32, [POINTER(TvcTensor), POINTER(TvcTensor), c_void_p, c_double, c_int32,
                              c_int32, c_int32, c_void_p, c_size_t, POINTER(HopmStats), c_void_p]),
     "tvc_quantize": (c_int32, [POINTER(TvcTensor), c_void_p, c_int32, c_void_p, c_int32, c_void_p]),
+    "tvc_backward_x_workspace_bytes": (c_size_t, [POINTER(TvcTensor), c_int32]),
+    "tvc_backward_x": (c_int32, [POINTER(TvcTensor), c_int32, c_void_p, c_void_p, c_void_p, c_size_t,
+                                 c_void_p]),
+    "tvc_backward_A": (c_int32, [c_int32, POINTER(c_int64), c_int32, c_int32, c_void_p, c_void_p,
+                                 c_void_p, c_double, c_double, c_void_p]),
+    "tvc_leave_one_out": (c_int32, [POINTER(TvcTensor), c_void_p, c_uint32, c_void_p, c_void_p, c_size_t,
+                                    c_void_p]),
+    "tvc_rank_update_workspace_bytes": (c_size_t, [c_int32, POINTER(c_int64), c_int32]),
+    "tvc_rank_update": (c_int32, [c_int32, POINTER(c_int64), c_int32, c_void_p, c_double, c_int32,
+                                  c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "hopm_iterate_record": (c_int32, [POINTER(TvcTensor), c_void_p, c_int32, c_void_p, c_size_t, c_void_p,
+                                      c_void_p, c_void_p]),
+    "hopm_backward_workspace_bytes": (c_size_t, [POINTER(TvcTensor), c_int32]),
+    "hopm_backward": (c_int32, [POINTER(TvcTensor), c_void_p, c_void_p, c_int32, c_void_p, c_double,
+                                c_double, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "tvc_probe_read": (c_int32, [c_void_p, c_size_t, c_void_p, c_int32, c_void_p]),
     "tvc_probe_copy": (c_int32, [c_void_p, c_void_p, c_size_t, c_int32, c_void_p]),
 }

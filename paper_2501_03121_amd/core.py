@@ -232,3 +232,114 @@ def probe_copy(src: torch.Tensor, dst: torch.Tensor, grid: int = 0) -> None:
     _require_cuda(src, dst)
     L.check(L.lib().tvc_probe_copy(src.data_ptr(), dst.data_ptr(), src.numel() * src.element_size(),
                                    int(grid), _stream()))
+
+
+# ---------------------------------------------------------------- derivatives
+def _dims_array(shape):
+    import ctypes
+    arr = (ctypes.c_int64 * len(shape))(*[int(n) for n in shape])
+    return arr
+
+
+def backward_x(A: torch.Tensor, g: torch.Tensor, mode: int, scale: torch.Tensor | None = None) -> torch.Tensor:
+    """dx = A contracted with g over every mode but `mode` (one pass over A)."""
+    desc = describe(A, scale)
+    acc = acc_dtype(desc.dtype)
+    _require_cuda(g)
+    if g.dtype != acc or g.numel() != A.numel() // A.shape[mode]:
+        raise TypeError("g has the wrong dtype or size")
+    dx = torch.empty(A.shape[mode], dtype=acc, device=A.device)
+    lib = L.lib()
+    need = lib.tvc_backward_x_workspace_bytes(desc, mode)
+    ws = _WS.get(need, A.device)
+    L.check(lib.tvc_backward_x(desc, mode, g.data_ptr(), dx.data_ptr(), _WS.ptr(ws), int(need), _stream()))
+    return dx
+
+
+def backward_A(g: torch.Tensor, x: torch.Tensor, mode: int, shape, alpha: float = 1.0, beta: float = 0.0,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+    """dA = alpha * (g outer x at `mode`) + beta * out."""
+    _require_cuda(g, x, out)
+    code = dtype_code(g)
+    if code not in (L.TVC_F32, L.TVC_F64) or x.dtype != g.dtype:
+        raise TypeError("g and x must both be float32 or both float64")
+    if out is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs out")
+        out = torch.empty(tuple(shape), dtype=g.dtype, device=g.device)
+    dims = _dims_array(shape)
+    L.check(L.lib().tvc_backward_A(len(shape), dims, code, int(mode), g.data_ptr(), x.data_ptr(),
+                                   out.data_ptr(), float(alpha), float(beta), _stream()))
+    return out
+
+
+def leave_one_out(A: torch.Tensor, v: torch.Tensor, modes=None, scale: torch.Tensor | None = None) -> torch.Tensor:
+    """out_m = A contracted with v_k over every k != m, for m in `modes`
+    (default all); v and the result are packed float64 vectors."""
+    desc = describe(A, scale)
+    _require_cuda(v)
+    if v.dtype != torch.float64 or v.numel() != sum(A.shape):
+        raise TypeError("v must be float64 with sum(dims) elements")
+    mask = (1 << A.dim()) - 1 if modes is None else sum(1 << int(m) for m in modes)
+    out = torch.zeros_like(v)
+    lib = L.lib()
+    need = lib.hopm_workspace_bytes(desc)
+    ws = _WS.get(need, A.device)
+    L.check(lib.tvc_leave_one_out(desc, v.data_ptr(), mask, out.data_ptr(), _WS.ptr(ws), int(need), _stream()))
+    return out
+
+
+def rank_update(shape, factors: torch.Tensor, coef: torch.Tensor, A: torch.Tensor | None = None,
+                alpha: float = 0.0, out: torch.Tensor | None = None, dtype=torch.float32) -> torch.Tensor:
+    """D = alpha * A + sum_r coef[r] * (outer product of the factor vectors of term r).
+
+    factors: float64 (R, sum(shape)); coef: float64 (R,)."""
+    _require_cuda(factors, coef, A, out)
+    R = int(coef.numel())
+    if out is None:
+        out = torch.empty(tuple(shape), dtype=dtype, device=factors.device)
+    code = dtype_code(out)
+    dims = _dims_array(shape)
+    lib = L.lib()
+    need = lib.tvc_rank_update_workspace_bytes(len(shape), dims, R)
+    ws = _WS.get(need, out.device)
+    L.check(lib.tvc_rank_update(len(shape), dims, code, A.data_ptr() if A is not None else None,
+                                float(alpha), R, factors.data_ptr(), coef.data_ptr(), out.data_ptr(),
+                                _WS.ptr(ws), int(need), _stream()))
+    return out
+
+
+def hopm_iterate_record(A: torch.Tensor, x: torch.Tensor, sweeps: int, norms: torch.Tensor,
+                        scale: torch.Tensor | None = None) -> torch.Tensor:
+    """hopm_iterate that writes ||y|| of every (sweep, j) step into `norms`."""
+    desc = describe(A, scale)
+    _require_cuda(x, norms)
+    if norms.dtype != torch.float64 or norms.numel() < sweeps * A.dim():
+        raise TypeError("norms must be float64 with sweeps * order elements")
+    lib = L.lib()
+    need = lib.hopm_workspace_bytes(desc)
+    ws = _WS.get(need, A.device)
+    stats = torch.zeros(32, dtype=torch.uint8, device=A.device)
+    L.check(lib.hopm_iterate_record(desc, x.data_ptr(), int(sweeps), _WS.ptr(ws), int(need),
+                                    stats.data_ptr(), norms.data_ptr(), _stream()))
+    return stats
+
+
+def hopm_backward(A: torch.Tensor, xs: torch.Tensor, norms: torch.Tensor, sweeps: int,
+                  gx: torch.Tensor | None, glam: float, gA_scale: float = 0.0, want_dA: bool = True,
+                  want_dx0: bool = False, scale: torch.Tensor | None = None):
+    """Reverse pass through `sweeps` HOPM sweeps; returns (dA or None, dx0 or None)."""
+    desc = describe(A, scale)
+    _require_cuda(xs, norms, gx)
+    acc = acc_dtype(desc.dtype)
+    dA = torch.empty(A.shape, dtype=acc, device=A.device) if want_dA else None
+    dx0 = torch.empty(sum(A.shape), dtype=torch.float64, device=A.device) if want_dx0 else None
+    lib = L.lib()
+    need = lib.hopm_backward_workspace_bytes(desc, int(sweeps))
+    ws = torch.empty(int(need) + 256, dtype=torch.uint8, device=A.device)
+    L.check(lib.hopm_backward(desc, xs.data_ptr(), norms.data_ptr(), int(sweeps),
+                              gx.data_ptr() if gx is not None else None, float(glam), float(gA_scale),
+                              dA.data_ptr() if dA is not None else None,
+                              dx0.data_ptr() if dx0 is not None else None,
+                              _WS.ptr(ws), int(need), _stream()))
+    return dA, dx0

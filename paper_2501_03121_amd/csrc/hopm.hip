@@ -86,7 +86,8 @@ enum { kFirstJ = 1, kLastJ = 2 };
 // x <- y / ||y||, mirrored into wv; delta and lambda bookkeeping in double.
 template <typename Acc>
 __global__ __launch_bounds__(kNormBlock) void k_normalize(const Acc* y, i64 n, double* x, Acc* wv,
-                                                          hopm_stats* st, int flags) {
+                                                          hopm_stats* st, int flags,
+                                                          double* norm_out) {
   __shared__ double sh[kNormBlock / kWave];
   double ss = 0.0;
   for (i64 i = threadIdx.x; i < n; i += kNormBlock) {
@@ -95,6 +96,7 @@ __global__ __launch_bounds__(kNormBlock) void k_normalize(const Acc* y, i64 n, d
   }
   ss = block_sum_1024(ss, sh);
   const double nrm = sqrt(ss);
+  if (norm_out && threadIdx.x == 0) *norm_out = nrm;
   if (!(nrm > 0.0) || !isfinite(nrm)) {
     if (threadIdx.x == 0) {
       st->status = TVC_EDEGENERATE;
@@ -195,6 +197,20 @@ void sweep_tvcs(const Layout& Lt, std::vector<std::array<i64, 4>>& out) {
       t /= n[m];
     }
   }
+  // leave-one-out chains on W_2 = A x_0 x_0 x_1 x_1 (modes 2..d-1 kept), each
+  // contracting modes k = d-1 .. 2 except the kept mode m
+  for (int m = 2; m < d; ++m) {
+    i64 left = Lt.R1, right = 1;   // left: modes before k still present
+    for (int k = d - 1; k >= 2; --k) {
+      if (k == m) {
+        left /= n[k];
+        right = n[k];
+        continue;
+      }
+      left /= n[k];
+      out.push_back({Lt.acc_dt, left, n[k], right});
+    }
+  }
 }
 
 Layout make_layout(const tvc_tensor* A) {
@@ -234,7 +250,9 @@ Layout make_layout(const tvc_tensor* A) {
     Lt.o_w1 = take(Lt.d >= 4 ? (size_t)Lt.R1 * ab : 0);
     Lt.o_Wa = take((size_t)Lt.R1 * ab);
     Lt.o_Wb = take(Lt.d >= 4 ? (size_t)(Lt.R1 / Lt.n[2]) * ab : 0);
-    const size_t c = Lt.d >= 4 ? (size_t)(Lt.R1 / Lt.n[Lt.d - 1]) * ab : 0;
+    i64 nmin = Lt.R1;
+    for (int k = 2; k < Lt.d; ++k) nmin = std::min(nmin, Lt.n[k]);
+    const size_t c = Lt.d >= 4 ? (size_t)(Lt.R1 / nmin) * ab : 0;
     Lt.o_Ca = take(c);
     Lt.o_Cb = take(c);
   } else {
@@ -260,6 +278,7 @@ struct Ctx {
   char* ws;
   hopm_stats* st;
   hipStream_t s;
+  double* norms = nullptr;   // optional: ||y|| of every (sweep, j) step
   template <typename P> P* at(size_t o) const { return (P*)(ws + o); }
 };
 
@@ -280,7 +299,8 @@ tvc_status normalize(const Ctx& c, const void* y, int j) {
   const Layout& Lt = *c.Lt;
   int flags = (j == 0 ? kFirstJ : 0) | (j == Lt.d - 1 ? kLastJ : 0);
   hipLaunchKernelGGL((k_normalize<Acc>), dim3(1), dim3(kNormBlock), 0, c.s, (const Acc*)y,
-                     Lt.n[j], c.x + Lt.off[j], c.at<Acc>(Lt.o_wv) + Lt.woff[j], c.st, flags);
+                     Lt.n[j], c.x + Lt.off[j], c.at<Acc>(Lt.o_wv) + Lt.woff[j], c.st, flags,
+                     c.norms ? c.norms + j : nullptr);
   TVC_TRY_HIP(hipGetLastError());
   return TVC_OK;
 }
@@ -394,7 +414,11 @@ tvc_status iterate(const Ctx& c, int sweeps) {
   hipLaunchKernelGGL((k_prepare<Acc>), dim3(g), dim3(256), 0, c.s, (const double*)c.x,
                      c.at<Acc>(Lt.o_wv), vo, c.st);
   TVC_TRY_HIP(hipGetLastError());
-  for (int i = 0; i < sweeps; ++i) TVC_TRY(sweep<Acc>(c));
+  Ctx ci = c;
+  for (int i = 0; i < sweeps; ++i) {
+    TVC_TRY(sweep<Acc>(ci));
+    if (ci.norms) ci.norms += Lt.d;
+  }
   return TVC_OK;
 }
 
@@ -416,14 +440,246 @@ tvc_status check_hopm_args(const tvc_tensor* A, double* x, void* ws, size_t ws_b
 }
 
 tvc_status iterate_any(const tvc_tensor* A, double* x, int sweeps, void* ws, size_t ws_bytes,
-                       hopm_stats* st, hipStream_t s) {
+                       hopm_stats* st, hipStream_t s, double* norms = nullptr) {
   Layout Lt = make_layout(A);
   TVC_TRY(check_hopm_args(A, x, ws, ws_bytes, Lt));
   if (sweeps < 1) return fail(TVC_EINVAL, "sweeps must be >= 1");
   if (!st) return fail(TVC_EINVAL, "stats pointer is NULL");
-  Ctx c{&Lt, A, x, (char*)ws, st, s};
+  if (norms && (uintptr_t)norms % 8) return fail(TVC_EINVAL, "norms misaligned");
+  Ctx c{&Lt, A, x, (char*)ws, st, s, norms};
   if (A->dtype == TVC_F64) return iterate<double>(c, sweeps);
   return iterate<float>(c, sweeps);
+}
+
+// ---------------------------------------------------------------- leave-one-out
+template <typename Acc>
+__global__ void k_to_double(const Acc* y, double* out, i64 n) {
+  for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+    out[i] = (double)y[i];
+}
+
+template <typename Acc>
+tvc_status to_double(const Ctx& c, const Acc* y, int m, double* out) {
+  const i64 n = c.Lt->n[m];
+  const int g = (int)std::max<i64>(1, std::min<i64>((n + 255) / 256, 64));
+  hipLaunchKernelGGL((k_to_double<Acc>), dim3(g), dim3(256), 0, c.s, y, out + c.Lt->off[m], n);
+  TVC_TRY_HIP(hipGetLastError());
+  return TVC_OK;
+}
+
+// out_m = A contracted with the vectors c.x over every mode but m, for every
+// m in `mask`: pass 1 (M) serves modes 0 and 1, pass 2 (W_2) the others,
+// each then a chain of small contractions of W_2 that keeps mode m.
+template <typename Acc>
+tvc_status leave_one_out(const Ctx& c, uint32_t mask, double* out) {
+  const Layout& Lt = *c.Lt;
+  const tvc_tensor* A = c.A;
+  const int d = Lt.d;
+  const i64* n = Lt.n;
+  const bool f8 = A->dtype == TVC_F8E4M3;
+  VecOffsets vo;
+  vo.d = d;
+  for (int m = 0; m < d; ++m) {
+    vo.n[m] = n[m];
+    vo.off[m] = Lt.off[m];
+    vo.woff[m] = Lt.woff[m];
+  }
+  hipLaunchKernelGGL((k_prepare<Acc>), dim3(16), dim3(256), 0, c.s, (const double*)c.x,
+                     c.at<Acc>(Lt.o_wv), vo, c.st);
+  TVC_TRY_HIP(hipGetLastError());
+  Acc* wv = c.at<Acc>(Lt.o_wv);
+  Acc* y = c.at<Acc>(Lt.o_y);
+  if (d == 2) {
+    if (mask & 1u) {
+      TVC_TRY(run(c, A->dtype, A->data, n[0], n[1], 1, wv + Lt.woff[1], y,
+                  f8 ? A->slab_scale : nullptr, 1));
+      TVC_TRY(to_double<Acc>(c, y, 0, out));
+    }
+    if (mask & 2u) {
+      const Acc* w0 = wv + Lt.woff[0];
+      if (f8) {
+        Acc* sw = c.at<Acc>(Lt.o_w2);
+        TVC_TRY(kron<Acc>(c, 0, 1, sw, A->slab_scale, 1));
+        w0 = sw;
+      }
+      TVC_TRY(run(c, A->dtype, A->data, 1, n[0], n[1], w0, y, nullptr, 1));
+      TVC_TRY(to_double<Acc>(c, y, 1, out));
+    }
+    return TVC_OK;
+  }
+  Acc* Mm = c.at<Acc>(Lt.o_M);
+  if (mask & 3u) {
+    const Acc* w1 = wv + Lt.woff[2];
+    if (d >= 4) {
+      Acc* w1b = c.at<Acc>(Lt.o_w1);
+      TVC_TRY(kron<Acc>(c, 2, d, w1b, nullptr, 1));
+      w1 = w1b;
+    }
+    TVC_TRY(run(c, A->dtype, A->data, Lt.n01, Lt.R1, 1, w1, Mm, f8 ? A->slab_scale : nullptr, n[1]));
+    if (mask & 1u) {
+      TVC_TRY(run(c, Lt.acc_dt, Mm, n[0], n[1], 1, wv + Lt.woff[1], y, nullptr, 1));
+      TVC_TRY(to_double<Acc>(c, y, 0, out));
+    }
+    if (mask & 2u) {
+      TVC_TRY(run(c, Lt.acc_dt, Mm, 1, n[0], n[1], wv + Lt.woff[0], y, nullptr, 1));
+      TVC_TRY(to_double<Acc>(c, y, 1, out));
+    }
+  }
+  if (mask & ~3u) {
+    Acc* w2 = c.at<Acc>(Lt.o_w2);
+    Acc* Wa = c.at<Acc>(Lt.o_Wa);
+    TVC_TRY(kron<Acc>(c, 0, 2, w2, f8 ? A->slab_scale : nullptr, n[1]));
+    TVC_TRY(run(c, A->dtype, A->data, 1, Lt.n01, Lt.R1, w2, Wa, nullptr, 1));
+    for (int m = 2; m < d; ++m) {
+      if (!(mask & (1u << m))) continue;
+      const Acc* src = Wa;
+      Acc* bufs[2] = {c.at<Acc>(Lt.o_Ca), c.at<Acc>(Lt.o_Cb)};
+      int bi = 0;
+      i64 left = Lt.R1, right = 1;
+      for (int k = d - 1; k >= 2; --k) {
+        left /= n[k];
+        if (k == m) {
+          right = n[k];
+          continue;
+        }
+        TVC_TRY(run(c, Lt.acc_dt, src, left, n[k], right, wv + Lt.woff[k], bufs[bi], nullptr, 1));
+        src = bufs[bi];
+        bi ^= 1;
+      }
+      TVC_TRY(to_double<Acc>(c, src, m, out));
+    }
+  }
+  return TVC_OK;
+}
+
+// ---------------------------------------------------------------- reverse pass
+// One step s = (sweep i, mode j) of the reverse pass through Gauss-Seidel
+// sweeps, in one workgroup:
+//   state before the step: x_m = xs_{i+1}[m] for m < j, xs_i[m] for m > j
+//   ybar = (xbar_j - x_j <x_j, xbar_j>) / ||y|| + seed * x_j,  x_j = xs_{i+1}[j]
+//   vecs = state with ybar at mode j (the operand of the leave-one-out pass),
+//   factor slot = the same vectors (one rank-1 term of dA), xbar_j = 0.
+__global__ __launch_bounds__(kNormBlock) void k_step_adjoint(const double* xs_i, const double* xs_i1,
+                                                             VecOffsets vo, int j, const double* norm,
+                                                             double seed, double* xbar, double* vecs,
+                                                             double* factor) {
+  __shared__ double sh[kNormBlock / kWave];
+  const i64 o = vo.off[j], n = vo.n[j];
+  double dot = 0.0;
+  for (i64 i = threadIdx.x; i < n; i += kNormBlock) dot += xs_i1[o + i] * xbar[o + i];
+  dot = block_sum_1024(dot, sh);
+  const double nrm = *norm;
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  for (i64 i = threadIdx.x; i < n; i += kNormBlock) {
+    const double xj = xs_i1[o + i];
+    const double yb = (xbar[o + i] - xj * dot) * inv + seed * xj;
+    vecs[o + i] = yb;
+    factor[o + i] = yb;
+    xbar[o + i] = 0.0;
+  }
+  for (int m = 0; m < vo.d; ++m) {
+    if (m == j) continue;
+    const double* src = m < j ? xs_i1 : xs_i;
+    for (i64 i = threadIdx.x; i < vo.n[m]; i += kNormBlock) {
+      const double v = src[vo.off[m] + i];
+      vecs[vo.off[m] + i] = v;
+      factor[vo.off[m] + i] = v;
+    }
+  }
+}
+
+// xbar_m += lo_m for every m != j
+__global__ void k_accumulate(double* xbar, const double* lo, VecOffsets vo, int j) {
+  for (int m = 0; m < vo.d; ++m) {
+    if (m == j) continue;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < vo.n[m];
+         i += (i64)gridDim.x * blockDim.x)
+      xbar[vo.off[m] + i] += lo[vo.off[m] + i];
+  }
+}
+
+__global__ void k_copy_f64(const double* s, double* d, i64 n, double v, int fill) {
+  for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+    d[i] = fill ? v : s[i];
+}
+
+struct BwLayout {
+  Layout lo;             // leave-one-out workspace (at offset 0)
+  size_t o_xbar = 0, o_vecs = 0, o_lo = 0, o_fac = 0, o_coef = 0, o_rank = 0, total = 0;
+  size_t rank_bytes = 0;
+  int terms = 0;
+};
+
+BwLayout make_bw_layout(const tvc_tensor* A, int sweeps) {
+  BwLayout b;
+  b.lo = make_layout(A);
+  const size_t ns = (size_t)b.lo.nsum;
+  b.terms = sweeps * A->order;
+  size_t o = b.lo.total;
+  auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
+  b.o_xbar = take(ns * 8);
+  b.o_vecs = take(ns * 8);
+  b.o_lo = take(ns * 8);
+  b.o_fac = take((size_t)b.terms * ns * 8);
+  b.o_coef = take((size_t)b.terms * 8);
+  b.rank_bytes = tvc_rank_update_workspace_bytes(A->order, A->dims, b.terms);
+  b.o_rank = take(b.rank_bytes);
+  b.total = o;
+  return b;
+}
+
+template <typename Acc>
+tvc_status backward(const tvc_tensor* A, const double* xs, const double* norms, int K,
+                    const double* gx, double glam, double gA_scale, void* dA, double* dx0,
+                    char* ws, const BwLayout& b, hipStream_t s) {
+  const Layout& Lt = b.lo;
+  const int d = Lt.d;
+  const i64 ns = Lt.nsum;
+  double* xbar = (double*)(ws + b.o_xbar);
+  double* vecs = (double*)(ws + b.o_vecs);
+  double* lo = (double*)(ws + b.o_lo);
+  double* fac = (double*)(ws + b.o_fac);
+  double* coef = (double*)(ws + b.o_coef);
+  const int g = (int)std::max<i64>(1, std::min<i64>((ns + 255) / 256, 64));
+  hipLaunchKernelGGL(k_copy_f64, dim3(g), dim3(256), 0, s, gx, xbar, ns, 0.0, gx ? 0 : 1);
+  const int gc = (int)std::max<int>(1, std::min<int>((b.terms + 255) / 256, 64));
+  hipLaunchKernelGGL(k_copy_f64, dim3(gc), dim3(256), 0, s, (const double*)nullptr, coef,
+                     (i64)b.terms, 1.0, 1);
+  TVC_TRY_HIP(hipGetLastError());
+  VecOffsets vo;
+  vo.d = d;
+  for (int m = 0; m < d; ++m) {
+    vo.n[m] = Lt.n[m];
+    vo.off[m] = Lt.off[m];
+    vo.woff[m] = Lt.woff[m];
+  }
+  hopm_stats* st = (hopm_stats*)(ws + Lt.o_stats);
+  Ctx c{&Lt, A, vecs, ws, st, s, nullptr};
+  const uint32_t all = (d >= 32) ? 0xffffffffu : ((1u << d) - 1u);
+  for (int i = K - 1; i >= 0; --i) {
+    for (int j = d - 1; j >= 0; --j) {
+      const int step = i * d + j;
+      const double seed = (i == K - 1 && j == d - 1) ? glam : 0.0;
+      hipLaunchKernelGGL(k_step_adjoint, dim3(1), dim3(kNormBlock), 0, s, xs + (size_t)i * ns,
+                         xs + (size_t)(i + 1) * ns, vo, j, norms + step, seed, xbar, vecs,
+                         fac + (size_t)step * ns);
+      TVC_TRY_HIP(hipGetLastError());
+      TVC_TRY(leave_one_out<Acc>(c, all & ~(1u << j), lo));
+      hipLaunchKernelGGL(k_accumulate, dim3(g), dim3(256), 0, s, xbar, (const double*)lo, vo, j);
+      TVC_TRY_HIP(hipGetLastError());
+    }
+  }
+  if (dx0) {
+    hipLaunchKernelGGL(k_copy_f64, dim3(g), dim3(256), 0, s, (const double*)xbar, dx0, ns, 0.0, 0);
+    TVC_TRY_HIP(hipGetLastError());
+  }
+  if (dA) {
+    const void* Ad = (gA_scale != 0.0) ? A->data : nullptr;
+    const int32_t rs = tvc_rank_update(d, A->dims, Lt.acc_dt, Ad, gA_scale, b.terms, fac, coef,
+                                       dA, ws + b.o_rank, b.rank_bytes, s);
+    if (rs != TVC_OK) return (tvc_status)rs;
+  }
+  return TVC_OK;
 }
 
 }  // namespace
@@ -518,6 +774,63 @@ int32_t hopm_solve(const tvc_tensor* A, const tvc_tensor* A_refine, double* x, d
   *h_out = h;
   if (!converged) return fail(TVC_ENOTCONVERGED, "max_sweeps reached");
   return TVC_OK;
+}
+
+int32_t hopm_iterate_record(const tvc_tensor* A, double* x, int32_t sweeps, void* ws,
+                            size_t ws_bytes, hopm_stats* d_stats, double* d_norms, void* stream) {
+  if (!d_norms) return fail(TVC_EINVAL, "d_norms is NULL");
+  return iterate_any(A, x, sweeps, ws, ws_bytes, d_stats, (hipStream_t)stream, d_norms);
+}
+
+int32_t tvc_leave_one_out(const tvc_tensor* A, const double* v, uint32_t modes, double* out,
+                          void* ws, size_t ws_bytes, void* stream) {
+  TVC_TRY(check_tensor(A, "A"));
+  if (A->order < 2) return fail(TVC_EINVAL, "leave-one-out needs order >= 2");
+  if (!v || !out) return fail(TVC_EINVAL, "v or out is NULL");
+  if ((uintptr_t)v % 8 || (uintptr_t)out % 8) return fail(TVC_EINVAL, "v or out misaligned");
+  Layout Lt = make_layout(A);
+  TVC_TRY(check_hopm_args(A, const_cast<double*>(v), ws, ws_bytes, Lt));
+  const size_t vb = (size_t)Lt.nsum * 8;
+  if (overlaps(out, vb, v, vb) || overlaps(out, vb, ws, ws_bytes) ||
+      overlaps(out, vb, A->data, (size_t)numel(A) * elem_bytes(A->dtype)))
+    return fail(TVC_EALIAS, "out overlaps v, the workspace or A");
+  const uint32_t all = A->order >= 32 ? 0xffffffffu : ((1u << A->order) - 1u);
+  if (modes & ~all) return fail(TVC_EINVAL, "modes has bits beyond the order");
+  hopm_stats* st = (hopm_stats*)((char*)ws + Lt.o_stats);
+  Ctx c{&Lt, A, const_cast<double*>(v), (char*)ws, st, (hipStream_t)stream, nullptr};
+  if (A->dtype == TVC_F64) return leave_one_out<double>(c, modes, out);
+  return leave_one_out<float>(c, modes, out);
+}
+
+size_t hopm_backward_workspace_bytes(const tvc_tensor* A, int32_t sweeps) {
+  if (check_tensor(A, "A") != TVC_OK || A->order < 2 || sweeps < 1) return 0;
+  return make_bw_layout(A, sweeps).total;
+}
+
+int32_t hopm_backward(const tvc_tensor* A, const double* xs, const double* norms, int32_t sweeps,
+                      const double* gx, double glam, double gA_scale, void* dA, double* dx0,
+                      void* ws, size_t ws_bytes, void* stream) {
+  TVC_TRY(check_tensor(A, "A"));
+  if (A->order < 2) return fail(TVC_EINVAL, "HOPM needs order >= 2");
+  if (sweeps < 1) return fail(TVC_EINVAL, "sweeps must be >= 1");
+  if (!xs || !norms) return fail(TVC_EINVAL, "xs or norms is NULL");
+  if (!dA && !dx0) return fail(TVC_EINVAL, "nothing to compute (dA and dx0 are NULL)");
+  if (gA_scale != 0.0 && A->dtype != TVC_F32 && A->dtype != TVC_F64)
+    return fail(TVC_EDTYPE, "gA_scale != 0 needs a TVC_F32 or TVC_F64 tensor");
+  BwLayout b = make_bw_layout(A, sweeps);
+  if (!ws || ws_bytes < b.total || (uintptr_t)ws % 256)
+    return fail(TVC_EWORKSPACE, "workspace of " + std::to_string(b.total) + " bytes required");
+  const size_t abytes = (size_t)numel(A) * elem_bytes(A->dtype);
+  const size_t dbytes = (size_t)numel(A) * acc_bytes(A->dtype);
+  if (overlaps(ws, ws_bytes, A->data, abytes) || (dA && overlaps(dA, dbytes, ws, ws_bytes)))
+    return fail(TVC_EALIAS, "workspace overlaps A or dA");
+  if (dA && dA != A->data && overlaps(dA, dbytes, A->data, abytes))
+    return fail(TVC_EALIAS, "dA overlaps A");
+  if (A->dtype == TVC_F64)
+    return backward<double>(A, xs, norms, sweeps, gx, glam, gA_scale, dA, dx0, (char*)ws, b,
+                            (hipStream_t)stream);
+  return backward<float>(A, xs, norms, sweeps, gx, glam, gA_scale, dA, dx0, (char*)ws, b,
+                         (hipStream_t)stream);
 }
 
 }  // extern "C"

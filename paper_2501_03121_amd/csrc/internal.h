@@ -15,7 +15,7 @@ typedef int64_t i64;
 
 // Launch roles: kernels launched for tvc_contract and for the HOPM sweep are
 // separate instantiations, so profiles attribute time to each.
-enum Role { kRoleContract = 0, kRoleHopm = 1 };
+enum Role { kRoleContract = 0, kRoleHopm = 1, kRoleRowWeights = 2 };
 
 // Kernel families for the (left, n_k, right) = (L, M, R) view of Sec. 3.
 enum Family { kRow = 0, kCol = 1, kSlab = 2 };
@@ -57,6 +57,13 @@ hipError_t run_tvc(int dtype, const void* A, i64 L, i64 M, i64 R, const void* w,
                    void* y, double alpha, double beta, const float* oscale,
                    i64 odiv, const TvcPlan& p, void* part, hipStream_t st,
                    int role = kRoleContract);
+
+// Rows whose weight vector depends on the row (row i uses
+// w + (i / wdiv) * wstride): y[i] = oscale[i / odiv] * sum_m A[i, m] * w_i[m].
+TvcPlan plan_rows_pw(int dtype, i64 L, i64 M, bool a16, bool w16);
+hipError_t run_rows_pw(int dtype, const void* A, i64 L, i64 M, const void* w, i64 wdiv,
+                       i64 wstride, void* y, const float* oscale, i64 odiv, const TvcPlan& p,
+                       void* part, hipStream_t st);
 
 // Convenience: plan + run with a workspace (error if too small).
 tvc_status tvc_run_auto(int dtype, const void* A, i64 L, i64 M, i64 R,

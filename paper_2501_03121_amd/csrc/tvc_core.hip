@@ -36,6 +36,8 @@ struct RowArgs {
   int nsplit, glog;
   Acc alpha, beta;
   const float* oscale; i64 odiv;
+  // kRoleRowWeights only: row i uses the weights w + (i / wdiv) * wstride
+  i64 wdiv, wstride;
 };
 
 template <typename Acc>
@@ -74,6 +76,8 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
     const i64 row0 = (t - s * ngroups) * RB;
     const i64 u0 = s * a.chunk;
     const i64 u1 = min(a.upr, u0 + a.chunk);
+    const Acc* wr = a.w;
+    if constexpr (ROLE == kRoleRowWeights) wr = a.w + (row0 / a.wdiv) * a.wstride;
     Acc acc[RB][EU];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
@@ -92,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
           raw[k][r] = (ok && row < a.L) ? U::load(a.A, row * a.upr + uk) : U::zero();
         }
         if (ok) {
-          load_w<Acc, EU>(a.w, uk * EU, wv[k]);
+          load_w<Acc, EU>(wr, uk * EU, wv[k]);
         } else {
 #pragma unroll
           for (int e = 0; e < EU; ++e) wv[k][e] = (Acc)0;
@@ -137,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_row_short(RowArgs<typename St<DT>::A
   const int rsub = lane >> a.glog;
   const bool active = sub < a.upr;
   Acc wv[EU];
-  if (active) {
+  if (active && ROLE != kRoleRowWeights) {
     load_w<Acc, EU>(a.w, (i64)sub * EU, wv);
   } else {
 #pragma unroll
@@ -157,6 +161,10 @@ __global__ __launch_bounds__(kBlock) void k_row_short(RowArgs<typename St<DT>::A
     for (int k = 0; k < kUnroll; ++k) {
       Acc v[EU];
       U::unpack(raw[k], v);
+      if constexpr (ROLE == kRoleRowWeights) {
+        const i64 row = base + (i64)k * P + rsub;
+        if (active && row < a.L) load_w<Acc, EU>(a.w + (row / a.wdiv) * a.wstride, (i64)sub * EU, wv);
+      }
       Acc s_ = (Acc)0;
 #pragma unroll
       for (int e = 0; e < EU; ++e) s_ = fma(v[e], wv[e], s_);
@@ -422,7 +430,7 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
   const dim3 grd(p.grid);
   if (p.family == kRow) {
     RowArgs<Acc> a{A, w, y, part, L, p.upr, p.chunk, p.nsplit, p.glog, (Acc)alpha, (Acc)beta,
-                   oscale, odiv};
+                   oscale, odiv, 1, 0};
     if (p.lng) {
       if (p.vec) {
         if (p.rb == 2) hipLaunchKernelGGL((k_row_long<DT, true, 2, ROLE>), grd, blk, 0, st, a);
@@ -467,6 +475,60 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
 }
 
 }  // namespace
+
+namespace {
+
+// Rows of length M whose weights change with the row: row i uses
+// w + (i / wdiv) * wstride.  Only the row family; one row per wave task.
+template <int DT>
+hipError_t run_rows_pw_dt(const void* A, i64 L, i64 M, const void* w_, i64 wdiv, i64 wstride,
+                          void* y_, const float* oscale, i64 odiv, const TvcPlan& p, void* part_,
+                          hipStream_t st) {
+  typedef typename St<DT>::Acc Acc;
+  RowArgs<Acc> a{A, (const Acc*)w_, (Acc*)y_, (Acc*)part_, L, p.upr, p.chunk, p.nsplit, p.glog,
+                 (Acc)1, (Acc)0, oscale, odiv, wdiv, wstride};
+  const dim3 blk(kBlock), grd(p.grid);
+  constexpr int RW = kRoleRowWeights;
+  if (p.lng) {
+    if (p.vec) hipLaunchKernelGGL((k_row_long<DT, true, 1, RW>), grd, blk, 0, st, a);
+    else hipLaunchKernelGGL((k_row_long<DT, false, 1, RW>), grd, blk, 0, st, a);
+  } else {
+    if (p.vec) hipLaunchKernelGGL((k_row_short<DT, true, RW>), grd, blk, 0, st, a);
+    else hipLaunchKernelGGL((k_row_short<DT, false, RW>), grd, blk, 0, st, a);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || p.nsplit == 1) return e;
+  const int g = (int)std::max<i64>(1, std::min<i64>(cdiv(L, kBlock), 4 * (i64)device_cus()));
+  hipLaunchKernelGGL((k_finalize<Acc, RW>), dim3(g), blk, 0, st, (const Acc*)part_, (Acc*)y_, L,
+                     p.nsplit, (i64)1, (Acc)1, (Acc)0, oscale, odiv);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+TvcPlan plan_rows_pw(int dtype, i64 L, i64 M, bool a16, bool w16) {
+  TvcPlan p = plan_tvc(dtype, L, M, 1, a16, w16);
+  if (p.lng && p.rb != 1) {
+    p.rb = 1;
+    const i64 groups = L;
+    p.tasks = groups * p.nsplit;
+    p.grid = grid_for(cdiv(p.tasks, kBlock / kWave), kRow, 8);
+  }
+  return p;
+}
+
+hipError_t run_rows_pw(int dtype, const void* A, i64 L, i64 M, const void* w, i64 wdiv,
+                       i64 wstride, void* y, const float* oscale, i64 odiv, const TvcPlan& p,
+                       void* part, hipStream_t st) {
+  switch (dtype) {
+    case TVC_F64: return run_rows_pw_dt<TVC_F64>(A, L, M, w, wdiv, wstride, y, oscale, odiv, p, part, st);
+    case TVC_F32: return run_rows_pw_dt<TVC_F32>(A, L, M, w, wdiv, wstride, y, oscale, odiv, p, part, st);
+    case TVC_F16: return run_rows_pw_dt<TVC_F16>(A, L, M, w, wdiv, wstride, y, oscale, odiv, p, part, st);
+    case TVC_BF16: return run_rows_pw_dt<TVC_BF16>(A, L, M, w, wdiv, wstride, y, oscale, odiv, p, part, st);
+    case TVC_F8E4M3: return run_rows_pw_dt<TVC_F8E4M3>(A, L, M, w, wdiv, wstride, y, oscale, odiv, p, part, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t run_tvc(int dtype, const void* A, i64 L, i64 M, i64 R, const void* w, void* y,
                    double alpha, double beta, const float* oscale, i64 odiv, const TvcPlan& p,
