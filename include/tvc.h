@@ -241,6 +241,57 @@ int32_t hopm_backward(const tvc_tensor* A, const double* xs, const double* norms
                       void* dA, double* dx0, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched HOPM (Sec. 3 HOPM, update order of Algorithm 1): many independent
+ * TVC_F32 instances of order 3..8 and uneven shapes, all swept `sweeps`
+ * times by one persistent kernel launch.  Each sweep of an instance is
+ * split into tiled passes over its tensor and single-workgroup vector
+ * steps; work items are (instance, phase, tile, sweep) in a device queue,
+ * and each instance advances through its phases on its own.  No host
+ * synchronisation: safe to capture in a hipGraph.
+ *
+ * The caller fills, per instance, A (device, dense last-order float32), x
+ * (device, double, the unit vectors back to back, updated in place), dims,
+ * order, and optionally tile_rows1 / tile_rows2 (rows of the [n0 n1][rest]
+ * view per work item of the two passes; 0 = derived from tile_elems).
+ * hopm_batch_prepare (host) completes the records (nt1, nt2, ws_offset,
+ * init_slot) and the plan; instances start in the given order (put the
+ * largest first).  The caller then copies the records to device memory and
+ * calls hopm_batch_run with a workspace of plan->ws_bytes bytes (256-byte
+ * aligned) and `count` device hopm_stats records.  grid = 0 picks 4
+ * workgroups per compute unit.  Every wait inside the kernel is bounded;
+ * hopm_batch_error copies the workspace's error word (0 = none) to a device
+ * uint32 after a run.  Calls sharing a workspace must not overlap.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const float* A;
+  double* x;
+  int64_t dims[8];
+  int32_t order;
+  int32_t tile_rows1;
+  int32_t tile_rows2;
+  int32_t nt1;             /* filled by hopm_batch_prepare */
+  int32_t nt2;             /* filled by hopm_batch_prepare */
+  int32_t reserved;
+  int64_t ws_offset;       /* filled by hopm_batch_prepare */
+  int64_t init_slot;       /* filled by hopm_batch_prepare */
+} hopm_batch_desc;
+
+typedef struct {
+  int64_t queue_slots;
+  int64_t initial_items;
+  size_t ws_bytes;
+  int32_t count;
+  int32_t sweeps;
+} hopm_batch_plan;
+
+int32_t hopm_batch_prepare(hopm_batch_desc* descs, int32_t count, int32_t sweeps,
+                           int32_t tile_elems, hopm_batch_plan* plan);
+int32_t hopm_batch_run(const hopm_batch_desc* d_descs, const hopm_batch_plan* plan,
+                       int32_t grid, void* ws, size_t ws_bytes, hopm_stats* d_stats,
+                       void* stream);
+int32_t hopm_batch_error(const void* ws, uint32_t* d_error_out, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Bandwidth probes (the analogue of the paper's STREAM yardstick, Sec. 5.1,
  * written for this library): read `bytes` bytes of src and write one float
  * per workgroup to sink (>= grid floats), or copy `bytes` bytes from src to

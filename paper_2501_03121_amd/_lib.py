@@ -52,8 +52,23 @@ class HopmBatchDesc(Structure):
         ("x", c_void_p),
         ("dims", c_int64 * 8),
         ("order", c_int32),
-        ("tile_elems", c_int32),
+        ("tile_rows1", c_int32),
+        ("tile_rows2", c_int32),
+        ("nt1", c_int32),
+        ("nt2", c_int32),
+        ("reserved", c_int32),
         ("ws_offset", c_int64),
+        ("init_slot", c_int64),
+    ]
+
+
+class HopmBatchPlan(Structure):
+    _fields_ = [
+        ("queue_slots", c_int64),
+        ("initial_items", c_int64),
+        ("ws_bytes", c_size_t),
+        ("count", c_int32),
+        ("sweeps", c_int32),
     ]
 
 
@@ -93,6 +108,9 @@ SIGNATURES = {
     "hopm_backward_workspace_bytes": (c_size_t, [POINTER(TvcTensor), c_int32]),
     "hopm_backward": (c_int32, [POINTER(TvcTensor), c_void_p, c_void_p, c_int32, c_void_p, c_double,
                                 c_double, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "hopm_batch_prepare": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p]),
+    "hopm_batch_run": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p, c_void_p]),
+    "hopm_batch_error": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "tvc_probe_read": (c_int32, [c_void_p, c_size_t, c_void_p, c_int32, c_void_p]),
     "tvc_probe_copy": (c_int32, [c_void_p, c_void_p, c_size_t, c_int32, c_void_p]),
 }
