@@ -292,6 +292,17 @@ int32_t hopm_batch_run(const hopm_batch_desc* d_descs, const hopm_batch_plan* pl
 int32_t hopm_batch_error(const void* ws, uint32_t* d_error_out, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Tuning (used by the autotuner): override launch parameters the dispatcher
+ * picks for one kernel family: 0 = rows (right extent 1), 1 = column
+ * streaming, 2 = small-right slabs.  blocks_per_cu caps the persistent grid
+ * at that many 256-thread workgroups per compute unit; split_m (family 1
+ * only: 1, 2 or 4) is the number of wave groups sharing one column tile.
+ * Values <= 0 restore the built-in choice.  Process-wide; set it while no
+ * other thread is launching contractions.
+ * ------------------------------------------------------------------------- */
+int32_t tvc_set_tuning(int32_t family, int32_t blocks_per_cu, int32_t split_m);
+
+/* ---------------------------------------------------------------------------
  * Bandwidth probes (the analogue of the paper's STREAM yardstick, Sec. 5.1,
  * written for this library): read `bytes` bytes of src and write one float
  * per workgroup to sink (>= grid floats), or copy `bytes` bytes from src to

@@ -206,6 +206,16 @@ int32_t tvc_contract(const tvc_tensor* A, int32_t mode, const void* x, void* y, 
                       wsleft ? (void*)wsp : nullptr, wsleft, st);
 }
 
+int32_t tvc_set_tuning(int32_t family, int32_t blocks_per_cu, int32_t split_m) {
+  if (family < 0 || family > 2) return fail(TVC_EINVAL, "family outside [0, 2]");
+  if (split_m > 0 && split_m != 1 && split_m != 2 && split_m != 4)
+    return fail(TVC_EINVAL, "split_m must be 1, 2 or 4");
+  if (blocks_per_cu > 64) return fail(TVC_EINVAL, "blocks_per_cu above 64");
+  tuning().blocks_per_cu[family] = blocks_per_cu > 0 ? blocks_per_cu : 0;
+  if (family == kCol) tuning().split_m = split_m > 0 ? split_m : 0;
+  return TVC_OK;
+}
+
 int32_t tvc_contract_plan(const tvc_tensor* A, int32_t mode, int32_t* info, int32_t n) {
   tvc_status s = check_tensor(A, "A");
   if (s != TVC_OK) return s;
