@@ -1,0 +1,76 @@
+"""Parity at the benchmark's full sizes and launch configuration: 1024^3 and
+32^6 float32 tensors (4.3 GB each).  Contractions are checked on sampled
+outputs that the oracle computes one by one from the exact host copy of the
+device bytes; HOPM sweeps against the float64 canonical oracle from the same
+start vectors."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2501_03121_amd as tvc
+from oracle import hopm as H
+from oracle import quant as Q
+from oracle import tvc as O
+from paper_2501_03121_amd import synth
+from _util import host
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1024, 1024, 1024), (32, 32, 32, 32, 32, 32)]
+SAMPLES = 2048
+
+
+def sample_lr(dims, k, seed):
+    u, _, v = O.matricized_dims(dims, k)
+    g = synth.rng(seed)
+    return np.stack([g.integers(0, u, SAMPLES), g.integers(0, v, SAMPLES)], axis=1)
+
+
+@pytest.mark.parametrize("dims", SHAPES, ids=["1024^3", "32^6"])
+def test_full_size_tvc_sampled(dev, dims):
+    A = synth.device_normal(dims, 100, dev)
+    Ah = A.cpu().numpy()
+    Ab, _ = tvc.quantize(A, "bf16")
+    Abh = Q.bf16_to_f64(Ab.cpu().view(torch.int16).numpy().view(np.uint16))
+    for k in range(len(dims)):
+        xh = synth.unit_vectors([dims[k]], 300 + k)[0].astype(np.float32)
+        x = torch.from_numpy(xh).to(dev)
+        lr = sample_lr(dims, k, 7 + k)
+        u, _, v = O.matricized_dims(dims, k)
+        y = host(tvc.contract(A, x, k)).reshape(u, v)[lr[:, 0], lr[:, 1]]
+        ref = O.tvc_sample(Ah, xh, k, lr)
+        assert O.rel_err(y, ref) < 1e-5, ("f32", dims, k, O.rel_err(y, ref))
+        yb = host(tvc.contract(Ab, x, k)).reshape(u, v)[lr[:, 0], lr[:, 1]]
+        refb = O.tvc_sample(Abh, xh, k, lr)
+        assert O.rel_err(yb, refb) < 1e-5, ("bf16", dims, k)
+
+
+@pytest.mark.parametrize("dims", SHAPES, ids=["1024^3", "32^6"])
+def test_full_size_hopm_sweep(dev, dims):
+    A, a = synth.device_planted(dims, 10.0, 0.1, 200, dev)
+    x0 = synth.warm_start(a, 0.9, 400)
+    x = tvc.pack_vectors(x0, dev)
+    r = tvc.read_stats(tvc.hopm_iterate(A, x, 1))
+    ref = H.hopm(A.cpu().numpy(), x0, sweeps=1)
+    got = np.split(host(x), np.cumsum(dims)[:-1])
+    for g, e in zip(got, ref.xs):
+        assert np.linalg.norm(g - e) < 1e-5
+    assert abs(r.lam - ref.lam) < 1e-5 * ref.lam
+
+
+@pytest.mark.timeout(600)
+def test_full_size_bf16_lambda_error(dev):
+    # 32^6 planted tensor: float64 oracle solve from the warm start vs the
+    # bf16-storage solve with one float32 refinement sweep
+    dims = SHAPES[1]
+    A, a = synth.device_planted(dims, 10.0, 0.1, 200, dev)
+    x0 = synth.warm_start(a, 0.9, 400)
+    ref = H.hopm(A.cpu().numpy(), x0, tol=1e-6, max_sweeps=40)
+    Ab, _ = tvc.quantize(A, "bf16")
+    x = tvc.pack_vectors(x0, dev)
+    r = tvc.hopm_solve(Ab, x, tol=1e-6, max_sweeps=200, A_refine=A, refine_sweeps=1)
+    assert r.status == 0
+    assert abs(r.lam - ref.lam) <= 1e-3 * ref.lam
+    x = tvc.pack_vectors(x0, dev)
+    r32 = tvc.hopm_solve(A, x, tol=1e-6, max_sweeps=200)
+    assert abs(r32.lam - ref.lam) <= 1e-5 * ref.lam
