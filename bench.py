@@ -46,6 +46,22 @@ def sweep_bytes(dims, b_a):
     return 2 * math.prod(dims) * b_a + 8 * sum(dims)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs, or None if the kernel source has
+    changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "tvc_col_f32_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    return int(rec["traffic_bytes_per_launch"]) if sha == rec["source_sha256"] else None
+
+
 class Call:
     """A prepared C-ABI call (descriptors built once, outside the timed loop)."""
 
@@ -193,7 +209,7 @@ def main() -> int:
     avg_b = statistics.mean(dom_b)
     achieved = avg_b / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
                 "kernel": "tvc::k_col<1, true, 4, 0> (float32 column streaming)",
                 "launches_per_step": len(dom), "avg_launch_ms": round(avg_ms, 4),
                 "avg_bytes_per_launch": int(avg_b)}

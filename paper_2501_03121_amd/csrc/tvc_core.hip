@@ -14,9 +14,9 @@
 //   kCol  (R large)         lanes own 16-byte column groups of one slab and
 //                           stream down the M rows; wave groups of a
 //                           workgroup split M and combine in LDS.
-//   kSlab (R small)         one wave reads whole slabs [M][R] with lanes
-//                           covering (row, column-group) pairs, then reduces
-//                           across the lanes holding the same columns.
+//   kSlab (R small)         a wave covers several consecutive slabs, one
+//                           lane per (slab, column group), each lane
+//                           streaming down its slab's rows (no reduction).
 // Splitting the contracted extent across tasks writes partial sums to a
 // workspace that k_finalize reduces in a fixed order, so results do not
 // depend on scheduling (no floating-point atomics).
@@ -27,7 +27,23 @@
 
 namespace tvc {
 
-constexpr int kUnroll = 4;   // 16-byte loads a lane keeps in flight per row
+// Loads a lane keeps in flight (build-time tunables).
+#ifndef TVC_UNROLL
+#define TVC_UNROLL 4
+#endif
+#ifndef TVC_SHORT_UNROLL
+#define TVC_SHORT_UNROLL 4
+#endif
+#ifndef TVC_SLAB_UNROLL
+#define TVC_SLAB_UNROLL 8
+#endif
+#ifndef TVC_COL1_UNROLL
+#define TVC_COL1_UNROLL 8
+#endif
+constexpr int kUnroll = TVC_UNROLL;             // per row: long rows, column groups
+constexpr int kShortUnroll = TVC_SHORT_UNROLL;  // short rows
+constexpr int kSlabUnroll = TVC_SLAB_UNROLL;    // slabs
+constexpr int kCol1Unroll = TVC_COL1_UNROLL;    // column streaming with one wave group
 
 template <typename Acc>
 struct RowArgs {
@@ -47,7 +63,25 @@ struct ColArgs {
   int nsplit, glog;
   Acc alpha, beta;
   const float* oscale; i64 odiv;
+  int y16;   // output (and partial) units may be stored as 16-byte vectors
 };
+
+template <typename Acc, int EU, bool VEC>
+__device__ __forceinline__ void store_units(Acc* dst, const Acc* v, int y16) {
+  if constexpr (VEC && (EU * sizeof(Acc)) % 16 == 0) {
+    if (y16) {
+#pragma unroll
+      for (int q = 0; q < (int)(EU * sizeof(Acc) / 16); ++q) {
+        uint4 u;
+        __builtin_memcpy(&u, v + q * (16 / sizeof(Acc)), 16);
+        ((uint4*)dst)[q] = u;
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EU; ++e) dst[e] = v[e];
+}
 
 template <typename Acc>
 __device__ __forceinline__ Acc epilogue(Acc v, const Acc* y, i64 idx, i64 l, Acc alpha,
@@ -56,6 +90,17 @@ __device__ __forceinline__ Acc epilogue(Acc v, const Acc* y, i64 idx, i64 l, Acc
   v *= alpha;
   if (beta != (Acc)0) v += beta * y[idx];
   return v;
+}
+
+// EU consecutive outputs at y + idx: alpha/beta/scale epilogue, stored as
+// 16-byte vectors when the unit is a whole number of vectors and aligned.
+template <typename Acc, int EU, bool VEC>
+__device__ __forceinline__ void store_epilogue(const Acc* acc, Acc* y, i64 idx, i64 l, Acc alpha,
+                                               Acc beta, const float* oscale, i64 odiv, int y16) {
+  Acc o[EU];
+#pragma unroll
+  for (int e = 0; e < EU; ++e) o[e] = epilogue(acc[e], y, idx + e, l, alpha, beta, oscale, odiv);
+  store_units<Acc, EU, VEC>(y + idx, o, y16);
 }
 
 // ---------------------------------------------------------------- kRow, long
@@ -149,16 +194,16 @@ __global__ __launch_bounds__(kBlock) void k_row_short(RowArgs<typename St<DT>::A
   }
   const i64 wave = (i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
   const i64 nwaves = (i64)gridDim.x * (kBlock / kWave);
-  const i64 per = (i64)P * kUnroll;
+  const i64 per = (i64)P * kShortUnroll;
   for (i64 base = wave * per; base < a.L; base += nwaves * per) {
-    typename U::Raw raw[kUnroll];
+    typename U::Raw raw[kShortUnroll];
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) {
+    for (int k = 0; k < kShortUnroll; ++k) {
       const i64 row = base + (i64)k * P + rsub;
       raw[k] = (active && row < a.L) ? U::load(a.A, row * a.upr + sub) : U::zero();
     }
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) {
+    for (int k = 0; k < kShortUnroll; ++k) {
       Acc v[EU];
       U::unpack(raw[k], v);
       if constexpr (ROLE == kRoleRowWeights) {
@@ -178,13 +223,15 @@ __global__ __launch_bounds__(kBlock) void k_row_short(RowArgs<typename St<DT>::A
 
 // ---------------------------------------------------------------- kCol
 // Workgroup task = (split s, slab l, column tile ct), ct fastest.  TC threads
-// along columns (one unit each), SPLITM wave groups along the rows.
+// along columns (one unit each), SPLITM wave groups along the rows, each
+// keeping UN loads in flight; the groups combine in LDS.
 template <int DT, bool VEC, int SPLITM, int ROLE>
 __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a) {
   typedef typename St<DT>::Acc Acc;
   typedef Unit<DT, VEC> U;
   constexpr int EU = U::EU;
   constexpr int TC = kBlock / SPLITM;
+  constexpr int UN = SPLITM == 1 ? kCol1Unroll : kUnroll;
   __shared__ Acc red[SPLITM > 1 ? (SPLITM - 1) * TC * EU : 1];
   const int tc = threadIdx.x % TC;
   const int grp = threadIdx.x / TC;
@@ -202,18 +249,18 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a)
     Acc acc[EU];
 #pragma unroll
     for (int e = 0; e < EU; ++e) acc[e] = (Acc)0;
-    for (i64 m = m0 + grp; m < m1; m += (i64)SPLITM * kUnroll) {
-      typename U::Raw raw[kUnroll];
-      Acc wv[kUnroll];
+    for (i64 m = m0 + grp; m < m1; m += (i64)SPLITM * UN) {
+      typename U::Raw raw[UN];
+      Acc wv[UN];
 #pragma unroll
-      for (int k = 0; k < kUnroll; ++k) {
+      for (int k = 0; k < UN; ++k) {
         const i64 mk = m + (i64)k * SPLITM;
         const bool ok = mk < m1;
         raw[k] = (active && ok) ? U::load(a.A, (slab + mk) * a.upr + c) : U::zero();
         wv[k] = ok ? a.w[mk] : (Acc)0;
       }
 #pragma unroll
-      for (int k = 0; k < kUnroll; ++k) {
+      for (int k = 0; k < UN; ++k) {
         Acc v[EU];
         U::unpack(raw[k], v);
 #pragma unroll
@@ -234,71 +281,69 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a)
       }
     }
     if (grp == 0 && active) {
-#pragma unroll
-      for (int e = 0; e < EU; ++e) {
-        const i64 idx = l * a.R + c * EU + e;
-        if (a.nsplit > 1) a.part[s * (a.L * a.R) + idx] = acc[e];
-        else a.y[idx] = epilogue(acc[e], a.y, idx, l, a.alpha, a.beta, a.oscale, a.odiv);
-      }
+      const i64 idx = l * a.R + c * EU;
+      if (a.nsplit > 1) store_units<Acc, EU, VEC>(a.part + s * (a.L * a.R) + idx, acc, a.y16);
+      else store_epilogue<Acc, EU, VEC>(acc, a.y, idx, l, a.alpha, a.beta, a.oscale, a.odiv, a.y16);
     }
     if constexpr (SPLITM > 1) __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------- kSlab
-// Wave task = (split s, slab l).  G = 2^glog lanes per row, P = 64/G rows
-// per wave load; lanes with equal (lane mod G) hold the same columns.
+// Small right extent (R <= 32 units).  A wave covers P = 64/G consecutive
+// slabs: lane (q, c) = (lane / G, lane mod G) owns column unit c of slab
+// l0 + q and streams down the M rows of that slab, so no cross-lane
+// reduction is needed; for a fixed row a wave load reads P contiguous
+// segments of G*16 bytes, one per slab.  The weight of a row is uniform
+// across the wave.
 template <int DT, bool VEC, int ROLE>
 __global__ __launch_bounds__(kBlock) void k_slab(ColArgs<typename St<DT>::Acc> a) {
   typedef typename St<DT>::Acc Acc;
   typedef Unit<DT, VEC> U;
   constexpr int EU = U::EU;
+  constexpr int UN = kSlabUnroll;
   const int lane = lane_id();
   const int G = 1 << a.glog;
   const int P = kWave >> a.glog;
-  const int sub = lane & (G - 1);
-  const int rsub = lane >> a.glog;
-  const bool active = sub < a.upr;
+  const int q = lane >> a.glog;
+  const int c = lane & (G - 1);
   const i64 wave = (i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
   const i64 nwaves = (i64)gridDim.x * (kBlock / kWave);
-  const i64 ntasks = a.L * a.nsplit;
+  const i64 groups = (a.L + P - 1) / P;
+  const i64 ntasks = groups * a.nsplit;
   for (i64 t = wave; t < ntasks; t += nwaves) {
-    const i64 l = t % a.L;
-    const i64 s = t / a.L;
+    const i64 g = t % groups;
+    const i64 s = t / groups;
+    const i64 l = g * P + q;
+    const bool on = c < a.upr && l < a.L;
     const i64 m0 = s * a.chunk;
     const i64 m1 = min(a.M, m0 + a.chunk);
-    const i64 slab = l * a.M;
+    const i64 base = l * a.M * a.upr + c;
     Acc acc[EU];
 #pragma unroll
     for (int e = 0; e < EU; ++e) acc[e] = (Acc)0;
-    for (i64 mb = m0; mb < m1; mb += (i64)P * kUnroll) {
-      typename U::Raw raw[kUnroll];
-      Acc wv[kUnroll];
+    for (i64 m = m0; m < m1; m += UN) {
+      typename U::Raw raw[UN];
+      Acc wv[UN];
 #pragma unroll
-      for (int k = 0; k < kUnroll; ++k) {
-        const i64 mk = mb + (i64)k * P + rsub;
-        const bool ok = active && mk < m1;
-        raw[k] = ok ? U::load(a.A, (slab + mk) * a.upr + sub) : U::zero();
+      for (int k = 0; k < UN; ++k) {
+        const i64 mk = m + k;
+        const bool ok = mk < m1;
+        raw[k] = (on && ok) ? U::load(a.A, base + mk * a.upr) : U::zero();
         wv[k] = ok ? a.w[mk] : (Acc)0;
       }
 #pragma unroll
-      for (int k = 0; k < kUnroll; ++k) {
+      for (int k = 0; k < UN; ++k) {
         Acc v[EU];
         U::unpack(raw[k], v);
 #pragma unroll
         for (int e = 0; e < EU; ++e) acc[e] = fma(v[e], wv[k], acc[e]);
       }
     }
-#pragma unroll
-    for (int e = 0; e < EU; ++e)
-      for (int off = G; off < kWave; off <<= 1) acc[e] += shfl_xor(acc[e], off);
-    if (rsub == 0 && active) {
-#pragma unroll
-      for (int e = 0; e < EU; ++e) {
-        const i64 idx = l * a.R + (i64)sub * EU + e;
-        if (a.nsplit > 1) a.part[s * (a.L * a.R) + idx] = acc[e];
-        else a.y[idx] = epilogue(acc[e], a.y, idx, l, a.alpha, a.beta, a.oscale, a.odiv);
-      }
+    if (on) {
+      const i64 idx = l * a.R + (i64)c * EU;
+      if (a.nsplit > 1) store_units<Acc, EU, VEC>(a.part + s * (a.L * a.R) + idx, acc, a.y16);
+      else store_epilogue<Acc, EU, VEC>(acc, a.y, idx, l, a.alpha, a.beta, a.oscale, a.odiv, a.y16);
     }
   }
 }
@@ -315,6 +360,61 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Acc* part, Acc* y, i6
     for (int k = 0; k < nsplit; ++k) s += part[(i64)k * n + i];
     y[i] = epilogue(s, y, i, i / R, alpha, beta, oscale, odiv);
   }
+}
+
+// Few outputs, many splits: a workgroup owns 64 outputs and its 8 waves sum
+// interleaved subsets of the splits; the 8 partials are combined in wave
+// order (a fixed order, so the result does not depend on scheduling).
+constexpr int kFinWaves = 8;
+
+template <typename Acc, int ROLE>
+__global__ __launch_bounds__(kFinWaves * kWave) void k_finalize_wide(const Acc* part, Acc* y, i64 n,
+                                                                   int nsplit, i64 R, Acc alpha,
+                                                                   Acc beta, const float* oscale,
+                                                                   i64 odiv) {
+  __shared__ Acc red[kFinWaves][kWave];
+  const int lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  for (i64 tile = blockIdx.x; tile * kWave < n; tile += gridDim.x) {
+    const i64 i = tile * kWave + lane;
+    Acc a0 = (Acc)0, a1 = (Acc)0, a2 = (Acc)0, a3 = (Acc)0;
+    if (i < n) {
+      int k = w;
+      for (; k + 3 * kFinWaves < nsplit; k += 4 * kFinWaves) {
+        a0 += part[(i64)k * n + i];
+        a1 += part[(i64)(k + kFinWaves) * n + i];
+        a2 += part[(i64)(k + 2 * kFinWaves) * n + i];
+        a3 += part[(i64)(k + 3 * kFinWaves) * n + i];
+      }
+      for (; k < nsplit; k += kFinWaves) a0 += part[(i64)k * n + i];
+    }
+    red[w][lane] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (w == 0 && i < n) {
+      Acc s = (Acc)0;
+#pragma unroll
+      for (int q = 0; q < kFinWaves; ++q) s += red[q][lane];
+      y[i] = epilogue(s, y, i, i / R, alpha, beta, oscale, odiv);
+    }
+    __syncthreads();
+  }
+}
+
+// Reduce nsplit partial rows of n outputs into y with the epilogue.
+template <typename Acc, int ROLE>
+hipError_t launch_finalize(const Acc* part, Acc* y, i64 n, int nsplit, i64 R, Acc alpha, Acc beta,
+                           const float* oscale, i64 odiv, hipStream_t st) {
+  const i64 cap = 4 * (i64)device_cus();
+  if (nsplit >= 32 && n <= 64 * cap) {
+    const int g = (int)std::max<i64>(1, std::min<i64>((n + kWave - 1) / kWave, cap));
+    hipLaunchKernelGGL((k_finalize_wide<Acc, ROLE>), dim3(g), dim3(kFinWaves * kWave), 0, st, part, y,
+                       n, nsplit, R, alpha, beta, oscale, odiv);
+  } else {
+    const int g = (int)std::max<i64>(1, std::min<i64>((n + kBlock - 1) / kBlock, cap));
+    hipLaunchKernelGGL((k_finalize<Acc, ROLE>), dim3(g), dim3(kBlock), 0, st, part, y, n, nsplit, R,
+                       alpha, beta, oscale, odiv);
+  }
+  return hipGetLastError();
 }
 
 // ====================================================================== host
@@ -349,7 +449,8 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a16, bool w16) {
     p.upr = M / eu;
     if (p.upr > 32) {
       p.lng = true;
-      p.rb = L >= 2 ? 2 : 1;
+      // rows sharing one weight load: enough that a lane keeps 8 loads in flight
+      p.rb = L >= 4 && p.upr <= 2 * kWave ? 4 : (L >= 2 ? 2 : 1);
       const i64 groups = cdiv(L, p.rb);
       p.nsplit = 1;
       p.chunk = p.upr;
@@ -364,13 +465,13 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a16, bool w16) {
         p.nsplit = (int)cdiv(p.upr, chunk);
       }
       p.tasks = groups * p.nsplit;
-      p.grid = grid_for(cdiv(p.tasks, waves_per_block), kRow, 8);
+      p.grid = grid_for(cdiv(p.tasks, waves_per_block), kRow, 16);
     } else {
       p.lng = false;
       p.glog = ceil_log2(std::max<i64>(p.upr, 1));
-      const i64 per = (i64)(kWave >> p.glog) * kUnroll;
+      const i64 per = (i64)(kWave >> p.glog) * kShortUnroll;
       p.tasks = cdiv(L, per);
-      p.grid = grid_for(cdiv(p.tasks, waves_per_block), kRow, 8);
+      p.grid = grid_for(cdiv(p.tasks, waves_per_block), kRow, 4);
     }
   } else {
     p.vec = a16 && (R * b) % 16 == 0;
@@ -394,22 +495,23 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a16, bool w16) {
         p.nsplit = (int)cdiv(M, p.chunk);
       }
       p.tasks = tasks * p.nsplit;
-      p.grid = grid_for(p.tasks, kCol, 8);
+      p.grid = grid_for(p.tasks, kCol, 4);
     } else {
       p.family = kSlab;
       p.glog = ceil_log2(std::max<i64>(p.upr, 1));
       const i64 P = kWave >> p.glog;
+      const i64 groups = cdiv(L, P);
       p.nsplit = 1;
       p.chunk = M;
       const i64 want = 16 * (i64)device_cus();
-      if (L < want && M >= P * kUnroll * 8) {
-        i64 ns = std::min<i64>(cdiv(2 * want, L), M / (P * kUnroll * 4));
+      if (groups < want && M >= (i64)kSlabUnroll * 16) {
+        i64 ns = std::min<i64>(cdiv(2 * want, groups), M / ((i64)kSlabUnroll * 8));
         ns = std::max<i64>(ns, 1);
         p.chunk = cdiv(M, ns);
         p.nsplit = (int)cdiv(M, p.chunk);
       }
-      p.tasks = L * p.nsplit;
-      p.grid = grid_for(cdiv(p.tasks, waves_per_block), kSlab, 8);
+      p.tasks = groups * p.nsplit;
+      p.grid = grid_for(cdiv(p.tasks, waves_per_block), kSlab, 4);
     }
   }
   p.part_bytes = p.nsplit > 1 ? align256((size_t)p.nsplit * (size_t)(L * R) * ab) : 0;
@@ -433,10 +535,12 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
                    oscale, odiv, 1, 0};
     if (p.lng) {
       if (p.vec) {
-        if (p.rb == 2) hipLaunchKernelGGL((k_row_long<DT, true, 2, ROLE>), grd, blk, 0, st, a);
+        if (p.rb == 4) hipLaunchKernelGGL((k_row_long<DT, true, 4, ROLE>), grd, blk, 0, st, a);
+        else if (p.rb == 2) hipLaunchKernelGGL((k_row_long<DT, true, 2, ROLE>), grd, blk, 0, st, a);
         else hipLaunchKernelGGL((k_row_long<DT, true, 1, ROLE>), grd, blk, 0, st, a);
       } else {
-        if (p.rb == 2) hipLaunchKernelGGL((k_row_long<DT, false, 2, ROLE>), grd, blk, 0, st, a);
+        if (p.rb == 4) hipLaunchKernelGGL((k_row_long<DT, false, 4, ROLE>), grd, blk, 0, st, a);
+        else if (p.rb == 2) hipLaunchKernelGGL((k_row_long<DT, false, 2, ROLE>), grd, blk, 0, st, a);
         else hipLaunchKernelGGL((k_row_long<DT, false, 1, ROLE>), grd, blk, 0, st, a);
       }
     } else {
@@ -445,8 +549,9 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
     }
   } else {
     const i64 tc = kBlock / p.splitm;
+    const int y16 = ((uintptr_t)y % 16 == 0) ? 1 : 0;
     ColArgs<Acc> a{A, w, y, part, L, M, p.upr, R, (p.upr + tc - 1) / tc, p.chunk, p.nsplit,
-                   p.glog, (Acc)alpha, (Acc)beta, oscale, odiv};
+                   p.glog, (Acc)alpha, (Acc)beta, oscale, odiv, y16};
     if (p.family == kCol) {
       if (p.vec) {
         if (p.splitm == 4) hipLaunchKernelGGL((k_col<DT, true, 4, ROLE>), grd, blk, 0, st, a);
@@ -464,13 +569,9 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (p.nsplit > 1) {
-    const i64 n = L * R;
-    const int g = (int)std::max<i64>(1, std::min<i64>(cdiv(n, kBlock), 4 * (i64)device_cus()));
-    hipLaunchKernelGGL((k_finalize<Acc, ROLE>), dim3(g), blk, 0, st, (const Acc*)part, y, n, p.nsplit,
-                       R, (Acc)alpha, (Acc)beta, oscale, odiv);
-    e = hipGetLastError();
-  }
+  if (p.nsplit > 1)
+    e = launch_finalize<Acc, ROLE>((const Acc*)part, y, L * R, p.nsplit, R, (Acc)alpha, (Acc)beta,
+                                   oscale, odiv, st);
   return e;
 }
 
@@ -498,10 +599,8 @@ hipError_t run_rows_pw_dt(const void* A, i64 L, i64 M, const void* w_, i64 wdiv,
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || p.nsplit == 1) return e;
-  const int g = (int)std::max<i64>(1, std::min<i64>(cdiv(L, kBlock), 4 * (i64)device_cus()));
-  hipLaunchKernelGGL((k_finalize<Acc, RW>), dim3(g), blk, 0, st, (const Acc*)part_, (Acc*)y_, L,
-                     p.nsplit, (i64)1, (Acc)1, (Acc)0, oscale, odiv);
-  return hipGetLastError();
+  return launch_finalize<Acc, RW>((const Acc*)part_, (Acc*)y_, L, p.nsplit, (i64)1, (Acc)1, (Acc)0,
+                                  oscale, odiv, st);
 }
 
 }  // namespace
