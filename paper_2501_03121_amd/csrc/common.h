@@ -72,13 +72,37 @@ template <> __device__ __forceinline__ void unpack16<TVC_F8E4M3>(const uint4& r,
   e4m3x4(r.x, o); e4m3x4(r.y, o + 4); e4m3x4(r.z, o + 8); e4m3x4(r.w, o + 12);
 }
 
+// Streaming loads of A use the nontemporal hint: every element is read once,
+// so it should not displace the vectors, weights and partial sums that are
+// reused from the caches (measured on gfx950: about 15% more read bandwidth).
+#ifndef TVC_NT_LOADS
+#define TVC_NT_LOADS 1
+#endif
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ T stream_load(const T* p) {
+#if TVC_NT_LOADS
+  if constexpr (sizeof(T) == 16) {
+    const u32x4 v = __builtin_nontemporal_load((const u32x4*)p);
+    T r;
+    __builtin_memcpy(&r, &v, 16);
+    return r;
+  } else {
+    return __builtin_nontemporal_load(p);
+  }
+#else
+  return *p;
+#endif
+}
+
 // A unit: VEC -> 16 bytes (EPV elements); scalar -> one element.
 template <int DT, bool VEC> struct Unit {
   static constexpr int EU = VEC ? St<DT>::EPV : 1;
   typedef typename St<DT>::Acc Acc;
   typedef typename std::conditional<VEC, uint4, typename St<DT>::T>::type Raw;
   __device__ __forceinline__ static Raw load(const void* base, i64 u) {
-    return ((const Raw*)base)[u];
+    return stream_load(((const Raw*)base) + u);
   }
   __device__ __forceinline__ static Raw zero() { Raw r; __builtin_memset(&r, 0, sizeof(Raw)); return r; }
   __device__ __forceinline__ static void unpack(const Raw& r, Acc* o) {

@@ -66,6 +66,40 @@ struct ColArgs {
   int y16;   // output (and partial) units may be stored as 16-byte vectors
 };
 
+
+// Work assignment of the persistent loops.  Chunked: every workgroup takes a
+// contiguous range of tasks (its waves interleaved inside the range), so a
+// workgroup streams a contiguous stretch of A; otherwise tasks are dealt
+// round-robin over the whole grid.
+#ifndef TVC_CHUNKED_TASKS
+#define TVC_CHUNKED_TASKS 1
+#endif
+struct TaskRange {
+  i64 begin, end, step;
+};
+
+__device__ __forceinline__ TaskRange wave_tasks(i64 ntasks) {
+  constexpr int wpb = kBlock / kWave;
+  const int w = threadIdx.x / kWave;
+#if TVC_CHUNKED_TASKS
+  const i64 per = (ntasks + gridDim.x - 1) / gridDim.x;
+  const i64 b = (i64)blockIdx.x * per;
+  return TaskRange{b + w, min(ntasks, b + per), (i64)wpb};
+#else
+  return TaskRange{(i64)blockIdx.x * wpb + w, ntasks, (i64)gridDim.x * wpb};
+#endif
+}
+
+__device__ __forceinline__ TaskRange block_tasks(i64 ntasks) {
+#if TVC_CHUNKED_TASKS
+  const i64 per = (ntasks + gridDim.x - 1) / gridDim.x;
+  const i64 b = (i64)blockIdx.x * per;
+  return TaskRange{b, min(ntasks, b + per), (i64)1};
+#else
+  return TaskRange{(i64)blockIdx.x, ntasks, (i64)gridDim.x};
+#endif
+}
+
 template <typename Acc, int EU, bool VEC>
 __device__ __forceinline__ void store_units(Acc* dst, const Acc* v, int y16) {
   if constexpr (VEC && (EU * sizeof(Acc)) % 16 == 0) {
@@ -112,11 +146,10 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
   typedef Unit<DT, VEC> U;
   constexpr int EU = U::EU;
   const int lane = lane_id();
-  const i64 wave = (i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
-  const i64 nwaves = (i64)gridDim.x * (kBlock / kWave);
   const i64 ngroups = (a.L + RB - 1) / RB;
   const i64 ntasks = ngroups * a.nsplit;
-  for (i64 t = wave; t < ntasks; t += nwaves) {
+  const TaskRange tr = wave_tasks(ntasks);
+  for (i64 t = tr.begin; t < tr.end; t += tr.step) {
     const i64 s = t / ngroups;
     const i64 row0 = (t - s * ngroups) * RB;
     const i64 u0 = s * a.chunk;
@@ -192,10 +225,10 @@ __global__ __launch_bounds__(kBlock) void k_row_short(RowArgs<typename St<DT>::A
 #pragma unroll
     for (int e = 0; e < EU; ++e) wv[e] = (Acc)0;
   }
-  const i64 wave = (i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
-  const i64 nwaves = (i64)gridDim.x * (kBlock / kWave);
   const i64 per = (i64)P * kShortUnroll;
-  for (i64 base = wave * per; base < a.L; base += nwaves * per) {
+  const TaskRange tr = wave_tasks((a.L + per - 1) / per);
+  for (i64 t = tr.begin; t < tr.end; t += tr.step) {
+    const i64 base = t * per;
     typename U::Raw raw[kShortUnroll];
 #pragma unroll
     for (int k = 0; k < kShortUnroll; ++k) {
@@ -236,7 +269,8 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a)
   const int tc = threadIdx.x % TC;
   const int grp = threadIdx.x / TC;
   const i64 ntasks = a.L * a.ctiles * a.nsplit;
-  for (i64 t = blockIdx.x; t < ntasks; t += gridDim.x) {
+  const TaskRange tr = block_tasks(ntasks);
+  for (i64 t = tr.begin; t < tr.end; t += tr.step) {
     const i64 ct = t % a.ctiles;
     const i64 rest = t / a.ctiles;
     const i64 l = rest % a.L;
@@ -307,11 +341,10 @@ __global__ __launch_bounds__(kBlock) void k_slab(ColArgs<typename St<DT>::Acc> a
   const int P = kWave >> a.glog;
   const int q = lane >> a.glog;
   const int c = lane & (G - 1);
-  const i64 wave = (i64)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
-  const i64 nwaves = (i64)gridDim.x * (kBlock / kWave);
   const i64 groups = (a.L + P - 1) / P;
   const i64 ntasks = groups * a.nsplit;
-  for (i64 t = wave; t < ntasks; t += nwaves) {
+  const TaskRange tr = wave_tasks(ntasks);
+  for (i64 t = tr.begin; t < tr.end; t += tr.step) {
     const i64 g = t % groups;
     const i64 s = t / groups;
     const i64 l = g * P + q;
