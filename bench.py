@@ -288,27 +288,29 @@ def run_extras(T, Hs, planted, dev, args):
                     "read_pct_peak": round(100 * rd / PEAK_HBM_GBS, 1)}
     log(json.dumps(out["probe"]))
 
-    # bf16 storage: every-mode contraction and one sweep
-    bf = {}
-    for i, (A, s) in enumerate(zip(T, SHAPES)):
-        Ab, _ = tvc.quantize(A, "bf16")
-        for k in range(len(s)):
-            x = torch.from_numpy(synth.unit_vectors([s[k]], 300 + k)[0]).float().to(dev)
-            y = torch.empty(A.numel() // s[k], dtype=torch.float32, device=dev)
-            tvc.contract(Ab, x, k, out=y)
-            torch.cuda.synchronize()
-            e0.record()
-            for _ in range(reps):
-                tvc.contract(Ab, x, k, out=y)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            gbs = tvc_bytes(s, k, 2) / (ms * 1e-3) / 1e9
-            bf[f"{len(s)}d_{s[0]}_mode{k}"] = {"ms": round(ms, 4), "GBps": round(gbs, 1),
-                                               "pct_peak": round(100 * gbs / PEAK_HBM_GBS, 1)}
-        del Ab
-    out["bf16_tvc"] = bf
-    log(json.dumps(bf))
+    # narrow storage: every-mode contraction in bf16, fp16 and E4M3 (+ slab scales)
+    ebytes = {"bf16": 2, "f16": 2, "e4m3": 1}
+    for fmt, b in ebytes.items():
+        res = {}
+        for i, (A, s) in enumerate(zip(T, SHAPES)):
+            Aq, S = tvc.quantize(A, fmt)
+            for k in range(len(s)):
+                x = torch.from_numpy(synth.unit_vectors([s[k]], 300 + k)[0]).float().to(dev)
+                y = torch.empty(A.numel() // s[k], dtype=torch.float32, device=dev)
+                tvc.contract(Aq, x, k, out=y, scale=S)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(reps):
+                    tvc.contract(Aq, x, k, out=y, scale=S)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                gbs = tvc_bytes(s, k, b) / (ms * 1e-3) / 1e9
+                res[f"{len(s)}d_{s[0]}_mode{k}"] = {"ms": round(ms, 4), "GBps": round(gbs, 1),
+                                                    "pct_peak": round(100 * gbs / PEAK_HBM_GBS, 1)}
+            del Aq, S
+        out[f"{fmt}_tvc"] = res
+        log(json.dumps({fmt: res}))
 
     # time to solution: float32 vs bf16 storage + one float32 refinement sweep,
     # from the same warm start (overlap 0.9 with the planted vectors)
@@ -317,7 +319,7 @@ def run_extras(T, Hs, planted, dev, args):
         Ab, _ = tvc.quantize(A, "bf16")
         x0 = synth.warm_start(planted[i], 0.9, 400 + i)
         res = {}
-        for label, store, refine in (("f32", A, None), ("bf16+f32refine", Ab, A)):
+        for label, store, refine in (("f32", A, None), ("bf16", Ab, None), ("bf16+f32refine", Ab, A)):
             runs = []
             for rep in range(3):
                 x = tvc.pack_vectors(x0, dev)
@@ -338,12 +340,133 @@ def run_extras(T, Hs, planted, dev, args):
             res[label] = {"seconds": round(tmed, 5), "sweeps": r.sweeps, "refine_sweeps": r.refine_sweeps,
                           "lambda": r.lam, "delta": r.delta, "status": r.status,
                           "min_overlap": round(min(overl), 6)}
-        res["speedup_bf16"] = round(res["f32"]["seconds"] / res["bf16+f32refine"]["seconds"], 3)
-        res["lambda_rel_diff"] = abs(res["bf16+f32refine"]["lambda"] - res["f32"]["lambda"]) / res["f32"]["lambda"]
+        res["speedup_bf16_refined"] = round(res["f32"]["seconds"] / res["bf16+f32refine"]["seconds"], 3)
+        res["speedup_bf16_only"] = round(res["f32"]["seconds"] / res["bf16"]["seconds"], 3)
+        res["lambda_rel_diff_refined"] = abs(res["bf16+f32refine"]["lambda"] - res["f32"]["lambda"]) / res["f32"]["lambda"]
+        res["lambda_rel_diff_bf16_only"] = abs(res["bf16"]["lambda"] - res["f32"]["lambda"]) / res["f32"]["lambda"]
         tts[f"{len(s)}d_{s[0]}"] = res
         del Ab
     out["time_to_solution"] = tts
     log(json.dumps(tts))
+    out["derivatives_256_4"] = run_derivatives(dev)
+    out["batch"] = run_batch(dev)
+    return out
+
+
+def run_derivatives(dev, K: int = 10):
+    """Backward of the contraction in every mode and the gradient through K
+    unrolled HOPM sweeps on a 256^4 float32 tensor (17.2 GB)."""
+    import torch
+
+    import paper_2501_03121_amd as tvc
+    from paper_2501_03121_amd import autograd as AG
+    from paper_2501_03121_amd import synth
+
+    dims = (256, 256, 256, 256)
+    n = math.prod(dims)
+    A = synth.device_normal(dims, 500, dev)
+    out = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    for k in range(4):
+        g = synth.device_normal((n // dims[k],), 600 + k, dev)
+        x = torch.from_numpy(synth.unit_vectors([dims[k]], 700 + k)[0]).float().to(dev)
+        tvc.backward_x(A, g, k)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            tvc.backward_x(A, g, k)
+        e1.record()
+        torch.cuda.synchronize()
+        msx = e0.elapsed_time(e1) / reps
+        dA = torch.empty_like(A)
+        tvc.backward_A(g, x, k, dims, out=dA)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            tvc.backward_A(g, x, k, dims, out=dA)
+        e1.record()
+        torch.cuda.synchronize()
+        msa = e0.elapsed_time(e1) / reps
+        bx = n * 4 + (n // dims[k]) * 4
+        ba = n * 4 + (n // dims[k]) * 4
+        out[f"mode{k}"] = {"dx_ms": round(msx, 3), "dx_GBps": round(bx / (msx * 1e-3) / 1e9, 1),
+                           "dA_ms": round(msa, 3), "dA_GBps": round(ba / (msa * 1e-3) / 1e9, 1)}
+        del dA, g
+    Ar = A.requires_grad_(True)
+    x0 = [torch.from_numpy(v).to(dev) for v in synth.unit_vectors(dims, 800)]
+    times = []
+    for _ in range(2):
+        Ar.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam = AG.hopm(Ar, K, *x0)[0]
+        loss = -lam * lam
+        loss.backward()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    # passes over A: 2 per forward sweep, 2 per backward step (d steps per
+    # sweep), plus reading A and writing dA once in the rank update
+    passes = 2 * K + 2 * K * 4
+    traffic = passes * n * 4 + 2 * n * 4
+    t = min(times)
+    out["unrolled_hopm_grad"] = {"sweeps": K, "seconds": round(t, 4), "passes_over_A": passes,
+                                 "GBps": round(traffic / t / 1e9, 1), "lambda": float(lam)}
+    log(json.dumps(out))
+    del Ar, A
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_batch(dev, count: int = 512, sweeps: int = 50):
+    """512 planted HOPM instances (order 3-5, dims per instance recipe, N(0,1)
+    + lambda a o b o ..., lambda ~ U[2, 20]) swept 50 times by one persistent
+    launch replayed from a graph; tiles and grid picked by the autotuner."""
+    import torch
+
+    import paper_2501_03121_amd as tvc
+    from paper_2501_03121_amd import batch as B
+    from paper_2501_03121_amd import synth
+
+    specs = synth.batch_instances(count, 900)
+    As, init = [], []
+    for i, (dims, lam) in enumerate(specs):
+        A = synth.device_normal(dims, 1000 + i, dev)
+        vecs = synth.unit_vectors(dims, 3000 + i, "normal")
+        outer = torch.ones((), dtype=torch.float64, device=dev)
+        for v in vecs:
+            outer = torch.tensordot(outer, torch.as_tensor(v, device=dev), dims=0)
+        A.add_(outer.float(), alpha=lam)
+        As.append(A)
+        init.append(tvc.pack_vectors(synth.unit_vectors(dims, 5000 + i), dev))
+    xs = [v.clone() for v in init]
+
+    def reset():
+        for x, v in zip(xs, init):
+            x.copy_(v)
+
+    total = sum(A.numel() for A in As)
+    te, grid, table = B.autotune(As, xs, sweeps, reset, tile_choices=(1 << 14, 1 << 16, 1 << 18),
+                                 grid_per_cu=(4, 8), reps=1)
+    bp = B.prepare(As, xs, sweeps, tile_elems=te, grid=grid)
+    g = B.capture(bp, reset)
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    err = B.error_word(bp)
+    res = B.results(bp)
+    t = min(times)
+    nbytes = 2 * total * 4 * sweeps
+    out = {"instances": count, "sweeps": sweeps, "elements": total, "tensor_GB": round(total * 4 / 1e9, 3),
+           "seconds": round(t, 4), "GBps": round(nbytes / t / 1e9, 1),
+           "pct_peak": round(100 * nbytes / t / 1e9 / PEAK_HBM_GBS, 1), "tile_elems": te, "grid": grid,
+           "error_word": err, "degenerate": sum(r.status != 0 for r in res),
+           "autotune": table}
+    log(json.dumps({k: v for k, v in out.items() if k != "autotune"}))
     return out
 
 
