@@ -85,6 +85,9 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--calib", action="store_true",
                     help="only run the read/copy probes of known size (counter calibration)")
+    ap.add_argument("--table1", action="store_true",
+                    help="only the hypersquare tensors of the paper's Table 1 (orders 2-10, float32): "
+                         "contraction in every mode and one HOPM sweep, %% of peak mean and std per order")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -114,6 +117,10 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"calib": {"read_bytes": a.numel() * 4, "copy_read_bytes": a.numel() * 4,
                                     "copy_write_bytes": a.numel() * 4}}), flush=True)
+        return 0
+
+    if args.table1:
+        print(json.dumps({"table1": run_table1(dev)}), flush=True)
         return 0
 
     # ------------------------------------------------------------ inputs
@@ -350,6 +357,58 @@ def run_extras(T, Hs, planted, dev, args):
     log(json.dumps(tts))
     out["derivatives_256_4"] = run_derivatives(dev)
     out["batch"] = run_batch(dev)
+    return out
+
+
+TABLE1 = {2: 30623, 3: 979, 4: 175, 5: 63, 6: 31, 7: 19, 8: 13, 9: 10, 10: 8}
+
+
+def run_table1(dev, reps: int = 5):
+    """The paper's Table 1 hypersquare tensors (dims chosen not to be
+    multiples of the vector length), here in float32 (same element counts,
+    3.3-4.3 GB): %-of-peak of the contraction in every mode and of one HOPM
+    sweep, with mean and unbiased std over the modes (the Table 2 statistic)."""
+    import torch
+
+    import paper_2501_03121_amd as tvc
+    from paper_2501_03121_amd import synth
+
+    out = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for d, n in TABLE1.items():
+        dims = (n,) * d
+        A = synth.device_normal(dims, 40 + d, dev)
+        per = []
+        for k in range(d):
+            x = torch.from_numpy(synth.unit_vectors([n], 50 + k)[0]).float().to(dev)
+            y = torch.empty(A.numel() // n, dtype=torch.float32, device=dev)
+            tvc.contract(A, x, k, out=y)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                tvc.contract(A, x, k, out=y)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            per.append(100 * tvc_bytes(dims, k, 4) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
+            del y
+        x = tvc.pack_vectors(synth.unit_vectors(dims, 60), dev)
+        tvc.hopm_iterate(A, x, 1)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            tvc.hopm_iterate(A, x, 1)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        sweep = 100 * sweep_bytes(dims, 4) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS
+        out[f"{n}^{d}"] = {"tvc_pct_mean": round(statistics.mean(per), 1),
+                           "tvc_pct_std": round(statistics.stdev(per), 1) if d > 1 else 0.0,
+                           "tvc_pct_per_mode": [round(p, 1) for p in per],
+                           "sweep_ms": round(ms, 3), "sweep_pct": round(sweep, 1)}
+        log(json.dumps({f"{n}^{d}": out[f"{n}^{d}"]}))
+        del A, x
+        torch.cuda.empty_cache()
     return out
 
 
