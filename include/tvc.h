@@ -120,11 +120,15 @@ int32_t tvc_contract(const tvc_tensor* A, int32_t mode, const void* x, void* y,
 /* Introspection of the launch tvc_contract(A, mode, ...) would make, for
  * tests, benchmarks and the autotuner.  Writes up to n values to info (host):
  * [0] family (0 = rows of the right-extent-1 view, 1 = column streaming,
- * 2 = small-right slabs), [1] 1 if 16-byte vector loads are used, [2] wave
+ * 2 = small-right slabs, 3 = small slabs staged through LDS), [1] 1 if
+ * 16-byte vector loads are used, [2] wave
  * groups per workgroup along the contracted extent (family 1), [3] number
  * of splits of the contracted extent (> 1 adds a finalize kernel), [4]
  * workgroups launched, [5] lanes per row (families 0 and 2, 0 = a wave per
- * row).  Assumes 16-byte aligned x.  Returns TVC_OK or an argument error. */
+ * row; family 3: lanes per output), [6] elements of each contiguous row after its last whole 16-byte
+ * vector (vector path only; such rows need only start on a 4-byte
+ * boundary), [7] full 16-byte vectors (or elements, scalar path) per row.
+ * Returns TVC_OK or an argument error. */
 int32_t tvc_contract_plan(const tvc_tensor* A, int32_t mode, int32_t* info, int32_t n);
 
 /* ---------------------------------------------------------------------------
@@ -294,10 +298,12 @@ int32_t hopm_batch_error(const void* ws, uint32_t* d_error_out, void* stream);
 /* ---------------------------------------------------------------------------
  * Tuning (used by the autotuner): override launch parameters the dispatcher
  * picks for one kernel family: 0 = rows (right extent 1), 1 = column
- * streaming, 2 = small-right slabs.  blocks_per_cu caps the persistent grid
- * at that many 256-thread workgroups per compute unit; split_m (family 1
- * only: 1, 2 or 4) is the number of wave groups sharing one column tile.
- * Values <= 0 restore the built-in choice.  Process-wide; set it while no
+ * streaming, 2 = small-right slabs, 3 = small slabs staged through LDS.
+ * blocks_per_cu caps the persistent grid at that many 256-thread workgroups
+ * per compute unit; for family 3 a negative value turns the family off (the
+ * dispatcher then uses families 0 and 2 for those shapes).  split_m (family
+ * 1 only: 1, 2 or 4) is the number of wave groups sharing one column tile.
+ * Values of 0 restore the built-in choice.  Process-wide; set it while no
  * other thread is launching contractions.
  * ------------------------------------------------------------------------- */
 int32_t tvc_set_tuning(int32_t family, int32_t blocks_per_cu, int32_t split_m);

@@ -114,17 +114,18 @@ def contract(A: torch.Tensor, x: torch.Tensor, mode: int, alpha: float = 1.0, be
     return out
 
 
-_FAMILY = {0: "row", 1: "col", 2: "slab"}
+_FAMILY = {0: "row", 1: "col", 2: "slab", 3: "stage"}
 
 
 def contract_plan(A: torch.Tensor, mode: int, scale: torch.Tensor | None = None) -> dict:
     """Which kernel tvc_contract(A, mode) launches, and with what shape."""
     import ctypes
     desc = describe(A, scale)
-    info = (ctypes.c_int32 * 6)()
-    L.check(L.lib().tvc_contract_plan(desc, mode, info, 6))
+    info = (ctypes.c_int32 * 8)()
+    L.check(L.lib().tvc_contract_plan(desc, mode, info, 8))
     return {"family": _FAMILY[info[0]], "vec": bool(info[1]), "split_m": info[2],
-            "nsplit": info[3], "grid": info[4], "lanes_per_row": info[5]}
+            "nsplit": info[3], "grid": info[4], "lanes_per_row": info[5], "tail": info[6],
+            "units_per_row": info[7]}
 
 
 @dataclass

@@ -139,11 +139,11 @@ int32_t tvc_version(void) { return 100; }
 static size_t contract_ws(const tvc_tensor* A, int32_t mode, i64 L, i64 M, i64 R) {
   size_t b = 0;
   if (A->dtype == TVC_F8E4M3 && mode == 0) b += align256((size_t)M * 4);
-  const bool a16 = ((uintptr_t)A->data % 16) == 0;
+  const bool a4 = ((uintptr_t)A->data % 4) == 0;
   // weights live in the workspace (aligned) for E4M3 mode 0; otherwise the
   // caller's x decides the vector path, which never needs more scratch.
-  TvcPlan p = plan_tvc(A->dtype, L, M, R, a16, true);
-  TvcPlan q = plan_tvc(A->dtype, L, M, R, a16, false);
+  TvcPlan p = plan_tvc(A->dtype, L, M, R, a4, true);
+  TvcPlan q = plan_tvc(A->dtype, L, M, R, a4, false);
   b += std::max(p.part_bytes, q.part_bytes);
   return b;
 }
@@ -207,7 +207,8 @@ int32_t tvc_contract(const tvc_tensor* A, int32_t mode, const void* x, void* y, 
 }
 
 int32_t tvc_set_tuning(int32_t family, int32_t blocks_per_cu, int32_t split_m) {
-  if (family < 0 || family > 2) return fail(TVC_EINVAL, "family outside [0, 2]");
+  if (family < 0 || family > 3) return fail(TVC_EINVAL, "family outside [0, 3]");
+  if (family == kStage) tuning().stage_off = blocks_per_cu < 0;
   if (split_m > 0 && split_m != 1 && split_m != 2 && split_m != 4)
     return fail(TVC_EINVAL, "split_m must be 1, 2 or 4");
   if (blocks_per_cu > 64) return fail(TVC_EINVAL, "blocks_per_cu above 64");
@@ -224,11 +225,13 @@ int32_t tvc_contract_plan(const tvc_tensor* A, int32_t mode, int32_t* info, int3
   if (!info || n < 0) return fail(TVC_EINVAL, "info is NULL");
   i64 L, M, R;
   mode_view(A, mode, &L, &M, &R);
+  const bool a4 = ((uintptr_t)A->data % 4) == 0;
   const bool a16 = ((uintptr_t)A->data % 16) == 0;
-  TvcPlan p = plan_tvc(A->dtype, L, M, R, a16, true);
-  const int32_t v[6] = {p.family, p.vec ? 1 : 0, p.splitm, p.nsplit, p.grid,
-                        (p.family == kCol || (p.family == kRow && p.lng)) ? 0 : (1 << p.glog)};
-  for (int i = 0; i < n && i < 6; ++i) info[i] = v[i];
+  TvcPlan p = plan_tvc(A->dtype, L, M, R, a4, true, a16);
+  const int32_t v[8] = {p.family, p.vec ? 1 : 0, p.splitm, p.nsplit, p.grid,
+                        (p.family == kCol || (p.family == kRow && p.lng)) ? 0 : (1 << p.glog),
+                        p.tail, (int32_t)std::min<i64>(p.upr, INT32_MAX)};
+  for (int i = 0; i < n && i < 8; ++i) info[i] = v[i];
   return TVC_OK;
 }
 

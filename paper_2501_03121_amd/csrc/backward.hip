@@ -41,32 +41,61 @@ __global__ void k_fill(Acc* p, i64 n, Acc v) {
     p[i] = v;
 }
 
-// dA[q, r] = alpha * g[l, r] * x[m] + beta * dA[q, r], q = l * M + m, in
-// 16-byte units when R is a multiple of the unit.
+// dA written as rows: row i (length n) holds
+//     alpha * s[i mod smod] * v[(i / vdiv) * n + c]  (+ beta * dA)
+// For R > 1 the rows are the (l, m) rows of the [L*M][R] view (s = x with
+// smod = M, v = g with vdiv = M); for R == 1 they are the l rows of the
+// [L][M] view (s = g, v = x shared by every row).  G lanes per row (a power
+// of two, at most 64), P = 64/G rows per wave step; rows longer than a wave
+// are cut into chunks of `chunk` units so that enough waves write at once.
+// Per row one index division; 16-byte nontemporal stores at dword alignment,
+// the ragged end of a row stored element by element.
 template <typename Acc, bool VEC, bool BETA>
-__global__ __launch_bounds__(kBlock) void k_outer(const Acc* g, const Acc* x, Acc* dA, i64 M, i64 R,
-                                                   i64 units, Acc alpha, Acc beta) {
+__global__ __launch_bounds__(kBlock) void k_outer_rows(const Acc* sv, i64 smod, const Acc* v, i64 vdiv,
+                                                        Acc* out, i64 rows, i64 n, i64 upr, int tail,
+                                                        int glog, i64 chunk, i64 nch, Acc alpha,
+                                                        Acc beta) {
   constexpr int EU = VEC ? (int)(16 / sizeof(Acc)) : 1;
-  const i64 upr = R / EU;
-  for (i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x; u < units;
-       u += (i64)gridDim.x * blockDim.x) {
-    const i64 q = u / upr;
-    const i64 r0 = (u - q * upr) * EU;
-    const i64 l = q / M;
-    const Acc xm = alpha * x[q - l * M];
-    Acc gv[EU];
-    load_w<Acc, EU>(g + l * R, r0, gv);
-    Acc* dst = dA + q * R + r0;
-    if constexpr (VEC) {
-      Acc o[EU];
-      if constexpr (BETA) load_w<Acc, EU>(dst, 0, o);
+  const int lane = lane_id();
+  const int G = 1 << glog, P = kWave >> glog;
+  const int sub = lane & (G - 1), rsub = lane >> glog;
+  const i64 nu = upr + (tail > 0 ? 1 : 0);
+  const i64 tasks = (rows + P - 1) / P * nch;
+  constexpr int wpb = kBlock / kWave;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  for (i64 t = (i64)blockIdx.x * wpb + w; t < tasks; t += (i64)gridDim.x * wpb) {
+    i64 rt, ch;
+    divmod(t, nch, rt, ch);
+    const i64 row = rt * P + rsub;
+    if (row >= rows) continue;
+    i64 vq, vr, sq, sr;
+    divmod(row, smod, sq, sr);
+    divmod(row, vdiv, vq, vr);
+    const Acc sc = alpha * sv[sr];
+    const Acc* vrow = v + vq * n;
+    Acc* orow = out + row * n;
+    const i64 u1 = min(nu, (ch + 1) * chunk);
+    for (i64 u = ch * chunk + sub; u < u1; u += G) {
+      const bool tl = tail > 0 && u == upr;
+      const i64 e = tl ? n - EU : u * EU;
+      Acc gv[EU], o[EU];
+      load_w<Acc, EU>(vrow, e, gv);
+      if constexpr (BETA) load_w<Acc, EU>(orow + e, 0, o);
 #pragma unroll
-      for (int e = 0; e < EU; ++e) o[e] = BETA ? fma(gv[e], xm, beta * o[e]) : gv[e] * xm;
-      uint4 st;
-      __builtin_memcpy(&st, o, 16);
-      *(uint4*)dst = st;
-    } else {
-      dst[0] = BETA ? fma(gv[0], xm, beta * dst[0]) : gv[0] * xm;
+      for (int q = 0; q < EU; ++q) o[q] = BETA ? fma(gv[q], sc, beta * o[q]) : gv[q] * sc;
+      if (!tl) {
+        if constexpr (VEC) {
+          u32x4 st;
+          __builtin_memcpy(&st, o, 16);
+          __builtin_nontemporal_store(st, (u32x4*)(orow + e));
+        } else {
+          orow[e] = o[0];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < EU; ++q)
+          if (q >= EU - tail) orow[e + q] = o[q];
+      }
     }
   }
 }
@@ -190,7 +219,7 @@ BxPlan plan_bx(const tvc_tensor* A, int mode) {
     b.o_ones = take((size_t)b.L * ab);
     for (int a16 = 0; a16 < 2; ++a16)
       for (int w16 = 0; w16 < 2; ++w16)
-        b.part = std::max(b.part, plan_rows_pw(A->dtype, b.L * b.M, b.R, a16, w16).part_bytes);
+        b.part = std::max(b.part, plan_rows_pw(A->dtype, b.L * b.M, b.R, a16, w16, b.M).part_bytes);
     b.part = std::max(b.part, plan_tvc(accdt, 1, b.L, b.M, true, true).part_bytes);
   }
   b.o_part = take(b.part);
@@ -259,8 +288,8 @@ int32_t tvc_backward_x(const tvc_tensor* A, int32_t mode, const void* g, void* d
   // middle: P[l, m] = sum_r A[l, m, r] g[l, r] (row (l, m) uses weights g[l, :]),
   // then dx[m] = sum_l P[l, m]
   void* P = w + b.o_P;
-  const bool a16 = (uintptr_t)A->data % 16 == 0, g16 = (uintptr_t)g % 16 == 0;
-  TvcPlan p = plan_rows_pw(A->dtype, b.L * b.M, b.R, a16, g16 && (b.R * ab) % 16 == 0);
+  const bool a4 = (uintptr_t)A->data % 4 == 0, g4 = (uintptr_t)g % 4 == 0;
+  TvcPlan p = plan_rows_pw(A->dtype, b.L * b.M, b.R, a4, g4, b.M);
   BX_TRY_HIP(run_rows_pw(A->dtype, A->data, b.L * b.M, b.R, g, b.M, b.R, P,
                          f8 ? A->slab_scale : nullptr, b.M * (b.L / A->dims[0]), p, w + b.o_part, st));
   void* ones = w + b.o_ones;
@@ -296,19 +325,33 @@ int32_t tvc_backward_A(int32_t order, const int64_t* dims, int32_t dtype, int32_
   if (overlaps(dA, (size_t)N * ab, g, (size_t)(L * R) * ab) || overlaps(dA, (size_t)N * ab, x, (size_t)M * ab))
     return fail(TVC_EALIAS, "dA overlaps g or x");
   hipStream_t st = (hipStream_t)stream;
-  const bool vec = (R * (i64)ab) % 16 == 0 && (uintptr_t)dA % 16 == 0 && (uintptr_t)g % 16 == 0;
-  const i64 units = vec ? N / (i64)(16 / ab) : N;
-  const dim3 grd(grid_(cdiv_(units, kBlock))), blk(kBlock);
+  // rows of the [L*M][R] view, or of the [L][M] view when R == 1
+  const bool byrow = R == 1;
+  const i64 rows = byrow ? L : L * M;
+  const i64 n = byrow ? M : R;
+  const i64 eu = (i64)(16 / ab);
+  const bool vec = n >= eu;
+  const i64 upr = vec ? n / eu : n;
+  const int tail = vec ? (int)(n % eu) : 0;
+  const i64 nu = upr + (tail > 0 ? 1 : 0);
+  int glog = 0;
+  while (((i64)1 << glog) < nu && glog < 6) ++glog;
+  const i64 chunk = nu > kWave ? std::min<i64>(nu, 16 * kWave) : nu;
+  const i64 nch = cdiv_(nu, chunk);
+  const i64 tasks = cdiv_(rows, kWave >> glog) * nch;
+  const dim3 grd(grid_(cdiv_(tasks, kBlock / kWave))), blk(kBlock);
   const bool b = beta != 0.0;
 #define OUTER(T)                                                                                   \
   do {                                                                                             \
-    const T* gp = (const T*)g; const T* xp = (const T*)x; T* dp = (T*)dA;                           \
+    const T* sp = (const T*)(byrow ? g : x); const T* vp = (const T*)(byrow ? x : g);              \
+    const i64 smod = byrow ? L : M, vdiv = byrow ? L : M;                                          \
+    T* dp = (T*)dA;                                                                                \
     if (vec) {                                                                                     \
-      if (b) hipLaunchKernelGGL((k_outer<T, true, true>), grd, blk, 0, st, gp, xp, dp, M, R, units, (T)alpha, (T)beta); \
-      else hipLaunchKernelGGL((k_outer<T, true, false>), grd, blk, 0, st, gp, xp, dp, M, R, units, (T)alpha, (T)beta); \
+      if (b) hipLaunchKernelGGL((k_outer_rows<T, true, true>), grd, blk, 0, st, sp, smod, vp, vdiv, dp, rows, n, upr, tail, glog, chunk, nch, (T)alpha, (T)beta); \
+      else hipLaunchKernelGGL((k_outer_rows<T, true, false>), grd, blk, 0, st, sp, smod, vp, vdiv, dp, rows, n, upr, tail, glog, chunk, nch, (T)alpha, (T)beta); \
     } else {                                                                                       \
-      if (b) hipLaunchKernelGGL((k_outer<T, false, true>), grd, blk, 0, st, gp, xp, dp, M, R, units, (T)alpha, (T)beta); \
-      else hipLaunchKernelGGL((k_outer<T, false, false>), grd, blk, 0, st, gp, xp, dp, M, R, units, (T)alpha, (T)beta); \
+      if (b) hipLaunchKernelGGL((k_outer_rows<T, false, true>), grd, blk, 0, st, sp, smod, vp, vdiv, dp, rows, n, upr, tail, glog, chunk, nch, (T)alpha, (T)beta); \
+      else hipLaunchKernelGGL((k_outer_rows<T, false, false>), grd, blk, 0, st, sp, smod, vp, vdiv, dp, rows, n, upr, tail, glog, chunk, nch, (T)alpha, (T)beta); \
     }                                                                                              \
   } while (0)
   if (dtype == TVC_F64) OUTER(double);

@@ -58,7 +58,7 @@ struct BatchHeader {
 };
 
 constexpr int kBThreads = 256;
-constexpr int kSpinLimit = 1 << 20;   // ~ seconds of s_sleep before giving up
+constexpr int kSpinLimit = 1 << 24;   // ~ seconds of short sleeps before giving up
 
 // Per-instance scratch (floats), 16-byte aligned pieces.
 struct InstLayout {
@@ -70,8 +70,7 @@ struct InstLayout {
 
 __host__ __device__ inline int64_t round4(int64_t v) { return (v + 3) & ~(int64_t)3; }
 
-__host__ __device__ inline InstLayout inst_layout(const int64_t* n, int d, int nt2) {
-  InstLayout L{};
+__host__ __device__ inline void inst_layout_to(InstLayout& L, const int64_t* n, int d, int nt2) {
   int64_t o = 0, ws = 0, xs = 0;
   L.nmax = 0;
   for (int m = 0; m < d; ++m) {
@@ -101,6 +100,11 @@ __host__ __device__ inline InstLayout inst_layout(const int64_t* n, int d, int n
   L.Cb = o; o += round4(c);
   L.y = o; o += round4(L.nmax);
   L.total = o;
+}
+
+__host__ __device__ inline InstLayout inst_layout(const int64_t* n, int d, int nt2) {
+  InstLayout L{};
+  inst_layout_to(L, n, d, nt2);
   return L;
 }
 
@@ -169,6 +173,20 @@ __device__ void wg_kron(const double* x, const InstLayout& L, const int64_t* n, 
                         float* w) {
   int64_t total = 1;
   for (int m = m0; m < m1; ++m) total *= n[m];
+  if (total <= (int64_t)UINT32_MAX) {
+    for (int64_t r = threadIdx.x; r < total; r += kBThreads) {
+      uint32_t rem = (uint32_t)r;
+      double p = 1.0;
+      for (int m = m1 - 1; m >= m0; --m) {
+        const uint32_t nm = (uint32_t)n[m];
+        const uint32_t q = rem / nm;
+        p *= x[L.off[m] + (rem - q * nm)];
+        rem = q;
+      }
+      w[r] = (float)p;
+    }
+    return;
+  }
   for (int64_t r = threadIdx.x; r < total; r += kBThreads) {
     int64_t rem = r;
     double p = 1.0;
@@ -181,8 +199,13 @@ __device__ void wg_kron(const double* x, const InstLayout& L, const int64_t* n, 
   }
 }
 
-__device__ inline uint32_t atomic_load_u32(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Queue flags and counters are polled with relaxed agent-scope loads (they
+// read the coherent copy without touching the caches); the one acquire fence
+// after a successful poll makes the producer's data visible.  On a chip whose
+// L2 is split across dies, an agent-scope acquire invalidates the local L2,
+// so it must not sit inside a polling loop.
+__device__ inline uint32_t relaxed_load_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Publish `count` items (instance inst, phase, tiles 0..count-1, sweep).
@@ -198,100 +221,168 @@ __device__ void wg_push(BatchHeader* hdr, Item* items, uint32_t* flags, int64_t 
     __syncthreads();
     return;
   }
-  for (int t = threadIdx.x; t < count; t += kBThreads) {
-    items[s0 + t] = Item{inst, phase, t, sweep};
-    __hip_atomic_store(&flags[s0 + t], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  for (int t = threadIdx.x; t < count; t += kBThreads) items[s0 + t] = Item{inst, phase, t, sweep};
+  // one release for the whole workgroup: everything it wrote (phase results
+  // and the items) is visible before any flag is
+  __syncthreads();
+  if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  for (int t = threadIdx.x; t < count; t += kBThreads)
+    __hip_atomic_store(&flags[s0 + t], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
 }
 
 // Count a finished tile; true for the workgroup that finished the last one.
 __device__ bool wg_tile_done(uint32_t* counter, int ntiles, uint32_t* sh_flag) {
-  __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t old = atomicAdd(counter, 1u);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this tile's results
+    const uint32_t old = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const bool last = old == (uint32_t)(ntiles - 1);
-    if (last) atomicExch(counter, 0u);
+    if (last) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every other tile's
+      __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     *sh_flag = last ? 1u : 0u;
   }
   __syncthreads();
-  const bool last = *sh_flag != 0;
-  if (last) __threadfence();
-  return last;
+  return *sh_flag != 0;
 }
 
 // ---------------------------------------------------------------- phases
+// Rows [r0, r1) of a float matrix with R columns: 16-byte loads at dword
+// alignment (row starts are 4-byte aligned), the ragged end of a row read as
+// one more unit over its last 4 columns with the overlap dropped.
+
+// P1: M[row] = sum_c A[row, c] * w1[c].  G lanes per row (a power of two,
+// at most 64), several row groups in flight per wave.
 __device__ void phase_p1(const BatchDesc& D, const InstLayout& L, float* s, int tile) {
-  const int64_t R1 = L.R1;
+  const int64_t R = L.R1;
   const int64_t r0 = (int64_t)tile * D.tile_rows1;
   const int64_t r1 = min(L.n01, r0 + D.tile_rows1);
-  const float* w1 = s + L.w1;
+  const float* w = s + L.w1;
   float* M = s + L.M;
-  int G = 1;
-  while (G < 64 && G < R1) G <<= 1;
-  const int P = kWave / G;
-  const int lane = lane_id();
-  const int sub = lane & (G - 1);
-  const int rsub = lane / G;
-  const int wave = threadIdx.x / kWave;
-  for (int64_t rb = r0 + (int64_t)wave * P; rb < r1; rb += (int64_t)(kBThreads / kWave) * P) {
-    const int64_t row = rb + rsub;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-    if (row < r1) {
-      const float* p = D.A + row * R1;
-      int64_t c = sub;
-      for (; c + 3 * (int64_t)G < R1; c += 4 * (int64_t)G) {
-        a0 = fmaf(p[c], w1[c], a0);
-        a1 = fmaf(p[c + G], w1[c + G], a1);
-        a2 = fmaf(p[c + 2 * G], w1[c + 2 * G], a2);
-        a3 = fmaf(p[c + 3 * G], w1[c + 3 * G], a3);
-      }
-      for (; c < R1; c += G) a0 = fmaf(p[c], w1[c], a0);
+  if (R < 4) {
+    for (int64_t row = r0 + threadIdx.x; row < r1; row += kBThreads) {
+      float acc = 0.f;
+      for (int64_t c = 0; c < R; ++c) acc = fmaf(D.A[row * R + c], w[c], acc);
+      M[row] = acc;
     }
-    float v = (a0 + a1) + (a2 + a3);
-    for (int off = G >> 1; off >= 1; off >>= 1) v += shfl_xor(v, off);
-    if (sub == 0 && row < r1) M[row] = v;
+    return;
+  }
+  constexpr int RU = 4;  // row groups in flight per wave
+  constexpr int NW = kBThreads / kWave;
+  const int64_t U = R / 4;
+  const int T = (int)(R % 4);
+  const int64_t nu = U + (T ? 1 : 0);
+  int g = 0;
+  while (((int64_t)1 << g) < nu && g < 6) ++g;
+  const int G = 1 << g, P = kWave >> g;
+  const int lane = lane_id();
+  const int sub = lane & (G - 1), rsub = lane >> g;
+  const int wave = threadIdx.x / kWave;
+  for (int64_t rb = r0 + (int64_t)wave * P * RU; rb < r1; rb += (int64_t)NW * P * RU) {
+    float acc[RU];
+#pragma unroll
+    for (int j = 0; j < RU; ++j) acc[j] = 0.f;
+    for (int64_t u = sub; u < nu; u += G) {
+      const bool tl = T != 0 && u == U;
+      const int64_t e = tl ? R - 4 : u * 4;
+      const int from = tl ? 4 - T : 0;
+      float wt[4];
+      load_w<float, 4>(w, e, wt);
+      uint4 raw[RU];
+#pragma unroll
+      for (int j = 0; j < RU; ++j) {
+        const int64_t row = rb + (int64_t)j * P + rsub;
+        raw[j] = row < r1 ? stream_load16(D.A + row * R + e) : uint4{0u, 0u, 0u, 0u};
+      }
+#pragma unroll
+      for (int j = 0; j < RU; ++j) {
+        float v[4];
+        unpack16<TVC_F32>(raw[j], v);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q >= from) acc[j] = fmaf(v[q], wt[q], acc[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < RU; ++j) {
+      float v = acc[j];
+      for (int off = G >> 1; off >= 1; off >>= 1) v += shfl_xor(v, off);
+      const int64_t row = rb + (int64_t)j * P + rsub;
+      if (sub == 0 && row < r1) M[row] = v;
+    }
   }
 }
 
+// P2: part[c] = sum over the tile's rows of w2[row] * A[row, c].  TC threads
+// per row own 16-byte column units, the 256/TC row groups of the workgroup
+// stream interleaved rows and combine in LDS in a fixed order.
 __device__ void phase_p2(const BatchDesc& D, const InstLayout& L, float* s, int tile, float* lds) {
-  const int64_t R1 = L.R1;
+  const int64_t R = L.R1;
   const int64_t r0 = (int64_t)tile * D.tile_rows2;
   const int64_t r1 = min(L.n01, r0 + D.tile_rows2);
   const float* w2 = s + L.w2;
-  float* part = s + L.part + (int64_t)tile * R1;
-  if (R1 <= kBThreads) {
-    int G = 1;
-    while (G < R1) G <<= 1;
-    const int P = kBThreads / G;
-    const int c = threadIdx.x % G;
-    const int rg = threadIdx.x / G;
-    float acc = 0.f;
-    if (c < R1)
-      for (int64_t row = r0 + rg; row < r1; row += P) acc = fmaf(w2[row], D.A[row * R1 + c], acc);
-    lds[threadIdx.x] = acc;
-    __syncthreads();
-    if (rg == 0 && c < R1) {
-      float t = 0.f;
-      for (int g = 0; g < P; ++g) t += lds[g * G + c];
-      part[c] = t;
+  float* part = s + L.part + (int64_t)tile * R;
+  if (R < 4) {
+    for (int64_t c = threadIdx.x; c < R; c += kBThreads) {
+      float acc = 0.f;
+      for (int64_t row = r0; row < r1; ++row) acc = fmaf(w2[row], D.A[row * R + c], acc);
+      part[c] = acc;
     }
-    __syncthreads();
-  } else {
-    for (int64_t cb = 0; cb < R1; cb += kBThreads) {
-      const int64_t c = cb + threadIdx.x;
-      if (c >= R1) continue;
-      float a0 = 0.f, a1 = 0.f;
-      int64_t row = r0;
-      for (; row + 1 < r1; row += 2) {
-        a0 = fmaf(w2[row], D.A[row * R1 + c], a0);
-        a1 = fmaf(w2[row + 1], D.A[(row + 1) * R1 + c], a1);
+    return;
+  }
+  constexpr int UN = 8;  // rows in flight per thread
+  const int64_t U = R / 4;
+  const int T = (int)(R % 4);
+  const int64_t nu = U + (T ? 1 : 0);
+  int g = 0;
+  while (((int64_t)1 << g) < nu && g < 8) ++g;
+  const int TC = 1 << g, RG = kBThreads >> g;
+  const int tc = threadIdx.x & (TC - 1), rg = threadIdx.x >> g;
+  for (int64_t cb = 0; cb < nu; cb += TC) {
+    const int64_t u = cb + tc;
+    const bool on = u < nu;
+    const bool tl = T != 0 && u == U;
+    const int64_t e = tl ? R - 4 : u * 4;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t row = r0 + rg; row < r1; row += (int64_t)RG * UN) {
+      uint4 raw[UN];
+      float wr[UN];
+#pragma unroll
+      for (int k = 0; k < UN; ++k) {
+        const int64_t rk = row + (int64_t)k * RG;
+        const bool ok = rk < r1;
+        raw[k] = (on && ok) ? stream_load16(D.A + rk * R + e) : uint4{0u, 0u, 0u, 0u};
+        wr[k] = ok ? w2[rk] : 0.f;
       }
-      if (row < r1) a0 = fmaf(w2[row], D.A[row * R1 + c], a0);
-      part[c] = a0 + a1;
+#pragma unroll
+      for (int k = 0; k < UN; ++k) {
+        float v[4];
+        unpack16<TVC_F32>(raw[k], v);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = fmaf(v[q], wr[k], acc[q]);
+      }
+    }
+    if (RG > 1) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) lds[(rg * TC + tc) * 4 + q] = acc[q];
+      __syncthreads();
+      if (rg == 0)
+        for (int h = 1; h < RG; ++h)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q] += lds[(h * TC + tc) * 4 + q];
+    }
+    if (rg == 0 && on) {
+      const int from = tl ? 4 - T : 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q >= from) part[e + q] = acc[q];
     }
   }
+  __syncthreads();
 }
 
 __device__ void phase_s1(const BatchDesc& D, const InstLayout& L, float* s, double* sh,
@@ -366,10 +457,9 @@ __device__ void phase_s2(const BatchDesc& D, const InstLayout& L, float* s, doub
     }
     const float* src = Wcur;
     int64_t t = wsize;
-    float* bufs[2] = {s + L.Ca, s + L.Cb};
     int bi = 0;
     for (int m = d - 1; m > j; --m) {
-      float* dst = (m == j + 1) ? s + L.y : bufs[bi];
+      float* dst = (m == j + 1) ? s + L.y : (bi ? s + L.Cb : s + L.Ca);
       wg_contract(src, t / n[m], n[m], 1, wv + L.woff[m], dst);
       __syncthreads();
       t /= n[m];
@@ -442,20 +532,24 @@ __global__ __launch_bounds__(kBThreads) void k_batch_run(const BatchDesc* descs,
                                                          uint32_t* counters, hopm_stats* stats,
                                                          BatchHeader* hdr, int64_t slots) {
   __shared__ double sh[kBThreads / kWave];
-  __shared__ float lds[kBThreads];
+  __shared__ float lds[4 * kBThreads];
   __shared__ uint32_t sh_u[2];
   __shared__ Item sh_item;
+  __shared__ BatchDesc sh_desc;
+  __shared__ InstLayout sh_layout;
   for (;;) {
     if (threadIdx.x == 0) {
       const uint32_t h = atomicAdd(&hdr->head, 1u);
       uint32_t ok = 0u;
       if ((int64_t)h < slots) {
         int spins = 0;
-        while (atomic_load_u32(&flags[h]) == 0u) {
-          if (atomic_load_u32(&hdr->error) != 0u || ++spins > kSpinLimit) break;
-          __builtin_amdgcn_s_sleep(63);
+        uint32_t f;
+        while ((f = relaxed_load_u32(&flags[h])) == 0u) {
+          if (relaxed_load_u32(&hdr->error) != 0u || ++spins > kSpinLimit) break;
+          __builtin_amdgcn_s_sleep(4);
         }
-        if (atomic_load_u32(&flags[h]) != 0u) {
+        if (f != 0u) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           ok = 1u;
           sh_item = items[h];
         } else {
@@ -466,11 +560,16 @@ __global__ __launch_bounds__(kBThreads) void k_batch_run(const BatchDesc* descs,
     }
     __syncthreads();
     if (sh_u[0] == 0u) return;
-    __threadfence();
     const Item it = sh_item;
+    // the instance's descriptor and scratch layout, once per item, in LDS
+    // (their arrays are indexed by mode at run time)
+    if (threadIdx.x == 0) {
+      sh_desc = descs[it.inst];
+      inst_layout_to(sh_layout, sh_desc.dims, sh_desc.order, sh_desc.nt2);
+    }
     __syncthreads();
-    const BatchDesc D = descs[it.inst];
-    const InstLayout L = inst_layout(D.dims, D.order, D.nt2);
+    const BatchDesc& D = sh_desc;
+    const InstLayout& L = sh_layout;
     float* s = (float*)(ws + D.ws_offset);
     hopm_stats* st = stats + it.inst;
     if (it.phase == kP1) {
@@ -479,7 +578,6 @@ __global__ __launch_bounds__(kBThreads) void k_batch_run(const BatchDesc* descs,
         wg_push(hdr, items, flags, slots, it.inst, kS1, 1, it.sweep, &sh_u[1]);
     } else if (it.phase == kS1) {
       phase_s1(D, L, s, sh, lds, st);
-      __threadfence();
       wg_push(hdr, items, flags, slots, it.inst, kP2, D.nt2, it.sweep, &sh_u[1]);
     } else if (it.phase == kP2) {
       phase_p2(D, L, s, it.tile, lds);
@@ -487,7 +585,6 @@ __global__ __launch_bounds__(kBThreads) void k_batch_run(const BatchDesc* descs,
         wg_push(hdr, items, flags, slots, it.inst, kS2, 1, it.sweep, &sh_u[1]);
     } else {
       phase_s2(D, L, s, sh, st);
-      __threadfence();
       if (it.sweep + 1 < sweeps) {
         wg_push(hdr, items, flags, slots, it.inst, kP1, D.nt1, it.sweep + 1, &sh_u[1]);
       } else if (threadIdx.x == 0) {

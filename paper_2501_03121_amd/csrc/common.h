@@ -72,37 +72,52 @@ template <> __device__ __forceinline__ void unpack16<TVC_F8E4M3>(const uint4& r,
   e4m3x4(r.x, o); e4m3x4(r.y, o + 4); e4m3x4(r.z, o + 8); e4m3x4(r.w, o + 12);
 }
 
+// 16-byte vectors that need only dword alignment.  Multi-dword global
+// accesses on CDNA need a dword-aligned address, not a 16-byte-aligned one,
+// so rows whose length is not a whole number of 16-byte vectors (odd
+// extents in float32, say) still stream as dwordx4 loads and stores.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4), aligned(4)));
+
 // Streaming loads of A use the nontemporal hint: every element is read once,
 // so it should not displace the vectors, weights and partial sums that are
 // reused from the caches (measured on gfx950: about 15% more read bandwidth).
 #ifndef TVC_NT_LOADS
 #define TVC_NT_LOADS 1
 #endif
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint4 stream_load16(const void* p) {
+#if TVC_NT_LOADS
+  const u32x4 v = __builtin_nontemporal_load((const u32x4*)p);
+#else
+  const u32x4 v = *(const u32x4*)p;
+#endif
+  uint4 r;
+  __builtin_memcpy(&r, &v, 16);
+  return r;
+}
 
 template <typename T>
 __device__ __forceinline__ T stream_load(const T* p) {
 #if TVC_NT_LOADS
-  if constexpr (sizeof(T) == 16) {
-    const u32x4 v = __builtin_nontemporal_load((const u32x4*)p);
-    T r;
-    __builtin_memcpy(&r, &v, 16);
-    return r;
-  } else {
-    return __builtin_nontemporal_load(p);
-  }
+  return __builtin_nontemporal_load(p);
 #else
   return *p;
 #endif
 }
 
-// A unit: VEC -> 16 bytes (EPV elements); scalar -> one element.
+// A unit: VEC -> 16 bytes (EPV elements) at a dword-aligned address;
+// scalar -> one element.  Units are addressed by their first element.
 template <int DT, bool VEC> struct Unit {
   static constexpr int EU = VEC ? St<DT>::EPV : 1;
   typedef typename St<DT>::Acc Acc;
-  typedef typename std::conditional<VEC, uint4, typename St<DT>::T>::type Raw;
-  __device__ __forceinline__ static Raw load(const void* base, i64 u) {
-    return stream_load(((const Raw*)base) + u);
+  typedef typename St<DT>::T T;
+  typedef typename std::conditional<VEC, uint4, T>::type Raw;
+  __device__ __forceinline__ static Raw load(const void* base, i64 e) {
+    if constexpr (VEC) {
+      return stream_load16((const T*)base + e);
+    } else {
+      return stream_load((const T*)base + e);
+    }
   }
   __device__ __forceinline__ static Raw zero() { Raw r; __builtin_memset(&r, 0, sizeof(Raw)); return r; }
   __device__ __forceinline__ static void unpack(const Raw& r, Acc* o) {
@@ -114,14 +129,15 @@ template <int DT, bool VEC> struct Unit {
   }
 };
 
-// EU consecutive weights starting at element e (16-byte aligned when VEC).
+// EU consecutive weights starting at element e (dword-aligned vector loads
+// when they span whole 16-byte vectors).
 template <typename Acc, int EU>
 __device__ __forceinline__ void load_w(const Acc* w, i64 e, Acc* o) {
   if constexpr (EU * sizeof(Acc) >= 16) {
-    const uint4* p = (const uint4*)(w + e);
+    const u32x4* p = (const u32x4*)(w + e);
 #pragma unroll
     for (int q = 0; q < (int)(EU * sizeof(Acc) / 16); ++q) {
-      uint4 r = p[q];
+      const u32x4 r = p[q];
       if constexpr (sizeof(Acc) == 4) {
         o[4 * q + 0] = __uint_as_float(r.x); o[4 * q + 1] = __uint_as_float(r.y);
         o[4 * q + 2] = __uint_as_float(r.z); o[4 * q + 3] = __uint_as_float(r.w);
@@ -133,6 +149,23 @@ __device__ __forceinline__ void load_w(const Acc* w, i64 e, Acc* o) {
   } else {
 #pragma unroll
     for (int q = 0; q < EU; ++q) o[q] = w[e + q];
+  }
+}
+
+// EU consecutive values to dst (dword-aligned vector stores when they span
+// whole 16-byte vectors).
+template <typename Acc, int EU>
+__device__ __forceinline__ void store_w(Acc* dst, const Acc* v) {
+  if constexpr ((EU * sizeof(Acc)) % 16 == 0) {
+#pragma unroll
+    for (int q = 0; q < (int)(EU * sizeof(Acc) / 16); ++q) {
+      u32x4 u;
+      __builtin_memcpy(&u, v + q * (16 / sizeof(Acc)), 16);
+      ((u32x4*)dst)[q] = u;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < EU; ++e) dst[e] = v[e];
   }
 }
 
@@ -150,5 +183,18 @@ __device__ __forceinline__ Acc wave_sum(Acc v) {
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// q = a / b, r = a mod b for non-negative a, b > 0: 32-bit division when
+// both fit (task and row indices almost always do), 64-bit otherwise.
+__device__ __forceinline__ void divmod(i64 a, i64 b, i64& q, i64& r) {
+  if ((((uint64_t)a | (uint64_t)b) >> 32) == 0) {
+    const uint32_t qq = (uint32_t)a / (uint32_t)b;
+    q = qq;
+    r = (uint32_t)a - qq * (uint32_t)b;
+  } else {
+    q = a / b;
+    r = a - q * b;
+  }
+}
 
 }  // namespace tvc

@@ -18,12 +18,13 @@ typedef int64_t i64;
 enum Role { kRoleContract = 0, kRoleHopm = 1, kRoleRowWeights = 2 };
 
 // Kernel families for the (left, n_k, right) = (L, M, R) view of Sec. 3.
-enum Family { kRow = 0, kCol = 1, kSlab = 2 };
+enum Family { kRow = 0, kCol = 1, kSlab = 2, kStage = 3 };
 
 // Launch parameters chosen by plan_tvc (or forced by tvc_set_tuning).
 struct TvcPlan {
   int family = kRow;
-  bool vec = false;      // 16-byte units
+  bool vec = false;      // 16-byte units (dword-aligned rows)
+  int tail = 0;          // vector path: elements after the last full unit of a row
   bool lng = true;       // kRow: a wave per row (true) or several rows per wave
   int glog = 0;          // log2 lanes per row (short rows / slabs)
   int rb = 1;            // kRow long: rows sharing one weight load
@@ -34,10 +35,12 @@ struct TvcPlan {
   i64 tasks = 0;         // independent work items (waves or workgroups)
   int grid = 1;          // workgroups launched
   size_t part_bytes = 0; // partial-sum scratch (nsplit > 1)
+  i64 sb = 0;            // kStage: slabs per LDS block
 };
 
 struct Tuning {
-  int blocks_per_cu[3] = {0, 0, 0};
+  int blocks_per_cu[4] = {0, 0, 0, 0};
+  bool stage_off = false;  // never pick the LDS-staged family
   int split_m = 0;
   int unroll = 0;
 };
@@ -48,7 +51,10 @@ size_t elem_bytes(int dtype);
 size_t acc_bytes(int dtype);
 int device_cus();
 
-TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a16, bool w16);
+// a4 / w4: A / the weights start on a 4-byte boundary; a16: A starts on a
+// 16-byte boundary (the LDS-staged family needs it; false is always safe
+// for sizing workspaces, which the staged family never needs).
+TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16 = false);
 
 // y[l, r] = alpha * oscale[l / odiv] * sum_m A[l, m, r] * w[m] + beta * y[l, r]
 // w, y, part: accumulation type of `dtype` (double for TVC_F64, else float).
@@ -60,7 +66,9 @@ hipError_t run_tvc(int dtype, const void* A, i64 L, i64 M, i64 R, const void* w,
 
 // Rows whose weight vector depends on the row (row i uses
 // w + (i / wdiv) * wstride): y[i] = oscale[i / odiv] * sum_m A[i, m] * w_i[m].
-TvcPlan plan_rows_pw(int dtype, i64 L, i64 M, bool a16, bool w16);
+// wdiv: rows i and j share weights when i / wdiv == j / wdiv; the plan only
+// puts rows that share weights in one wave.
+TvcPlan plan_rows_pw(int dtype, i64 L, i64 M, bool a4, bool w4, i64 wdiv);
 hipError_t run_rows_pw(int dtype, const void* A, i64 L, i64 M, const void* w, i64 wdiv,
                        i64 wstride, void* y, const float* oscale, i64 odiv, const TvcPlan& p,
                        void* part, hipStream_t st);

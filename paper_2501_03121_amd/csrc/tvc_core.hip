@@ -17,6 +17,10 @@
 //   kSlab (R small)         a wave covers several consecutive slabs, one
 //                           lane per (slab, column group), each lane
 //                           streaming down its slab's rows (no reduction).
+//   kStage (M*R small)      whole slabs are copied through LDS in blocks
+//                           that are one contiguous stretch of A (fully
+//                           coalesced whatever M and R are), and the
+//                           outputs are computed from LDS.
 // Splitting the contracted extent across tasks writes partial sums to a
 // workspace that k_finalize reduces in a fixed order, so results do not
 // depend on scheduling (no floating-point atomics).
@@ -54,6 +58,8 @@ struct RowArgs {
   const float* oscale; i64 odiv;
   // kRoleRowWeights only: row i uses the weights w + (i / wdiv) * wstride
   i64 wdiv, wstride;
+  i64 ld;    // row length in elements (upr full units, then tail elements)
+  int tail;  // vector path: elements after the last full unit (< EU)
 };
 
 template <typename Acc>
@@ -63,58 +69,50 @@ struct ColArgs {
   int nsplit, glog;
   Acc alpha, beta;
   const float* oscale; i64 odiv;
-  int y16;   // output (and partial) units may be stored as 16-byte vectors
+  int tail;  // vector path: columns after the last full unit (< EU)
 };
 
 
 // Work assignment of the persistent loops.  Chunked: every workgroup takes a
 // contiguous range of tasks (its waves interleaved inside the range), so a
 // workgroup streams a contiguous stretch of A; otherwise tasks are dealt
-// round-robin over the whole grid.
-#ifndef TVC_CHUNKED_TASKS
-#define TVC_CHUNKED_TASKS 1
-#endif
+// round-robin over the whole grid.  Measured on gfx950: chunked ranges help
+// the long-row kernel (about 7% on 4 KB rows), round-robin dealing is 3-6%
+// better for the column, slab and short-row kernels.
 struct TaskRange {
   i64 begin, end, step;
 };
 
+template <bool CHUNKED>
 __device__ __forceinline__ TaskRange wave_tasks(i64 ntasks) {
   constexpr int wpb = kBlock / kWave;
-  const int w = threadIdx.x / kWave;
-#if TVC_CHUNKED_TASKS
-  const i64 per = (ntasks + gridDim.x - 1) / gridDim.x;
-  const i64 b = (i64)blockIdx.x * per;
-  return TaskRange{b + w, min(ntasks, b + per), (i64)wpb};
-#else
-  return TaskRange{(i64)blockIdx.x * wpb + w, ntasks, (i64)gridDim.x * wpb};
-#endif
+  // the wave index is uniform across the wave; saying so keeps task indices
+  // and row bases in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if constexpr (CHUNKED) {
+    const i64 per = (ntasks + gridDim.x - 1) / gridDim.x;
+    const i64 b = (i64)blockIdx.x * per;
+    return TaskRange{b + w, min(ntasks, b + per), (i64)wpb};
+  } else {
+    return TaskRange{(i64)blockIdx.x * wpb + w, ntasks, (i64)gridDim.x * wpb};
+  }
 }
 
 __device__ __forceinline__ TaskRange block_tasks(i64 ntasks) {
-#if TVC_CHUNKED_TASKS
-  const i64 per = (ntasks + gridDim.x - 1) / gridDim.x;
-  const i64 b = (i64)blockIdx.x * per;
-  return TaskRange{b, min(ntasks, b + per), (i64)1};
-#else
   return TaskRange{(i64)blockIdx.x, ntasks, (i64)gridDim.x};
-#endif
 }
 
-template <typename Acc, int EU, bool VEC>
-__device__ __forceinline__ void store_units(Acc* dst, const Acc* v, int y16) {
-  if constexpr (VEC && (EU * sizeof(Acc)) % 16 == 0) {
-    if (y16) {
+// EU consecutive values to dst; a ragged last unit stores only its elements
+// from..EU-1 (the ones not owned by the unit before it).
+template <typename Acc, int EU>
+__device__ __forceinline__ void store_units(Acc* dst, const Acc* v, int from) {
+  if (from == 0) {
+    store_w<Acc, EU>(dst, v);
+  } else {
 #pragma unroll
-      for (int q = 0; q < (int)(EU * sizeof(Acc) / 16); ++q) {
-        uint4 u;
-        __builtin_memcpy(&u, v + q * (16 / sizeof(Acc)), 16);
-        ((uint4*)dst)[q] = u;
-      }
-      return;
-    }
+    for (int e = 0; e < EU; ++e)
+      if (e >= from) dst[e] = v[e];
   }
-#pragma unroll
-  for (int e = 0; e < EU; ++e) dst[e] = v[e];
 }
 
 template <typename Acc>
@@ -126,75 +124,128 @@ __device__ __forceinline__ Acc epilogue(Acc v, const Acc* y, i64 idx, i64 l, Acc
   return v;
 }
 
-// EU consecutive outputs at y + idx: alpha/beta/scale epilogue, stored as
-// 16-byte vectors when the unit is a whole number of vectors and aligned.
-template <typename Acc, int EU, bool VEC>
+// EU consecutive outputs at y + idx with the alpha/beta/scale epilogue.
+template <typename Acc, int EU>
 __device__ __forceinline__ void store_epilogue(const Acc* acc, Acc* y, i64 idx, i64 l, Acc alpha,
-                                               Acc beta, const float* oscale, i64 odiv, int y16) {
+                                               Acc beta, const float* oscale, i64 odiv, int from) {
   Acc o[EU];
 #pragma unroll
   for (int e = 0; e < EU; ++e) o[e] = epilogue(acc[e], y, idx + e, l, alpha, beta, oscale, odiv);
-  store_units<Acc, EU, VEC>(y + idx, o, y16);
+  store_units<Acc, EU>(y + idx, o, from);
 }
 
 // ---------------------------------------------------------------- kRow, long
 // One wave per (group of RB rows, chunk of the row).  Task t -> (chunk s,
 // row group g) with g fastest, so consecutive waves share a weight chunk.
+// A lane keeps KU units of each of the RB rows in flight, KU * RB = 8 loads
+// (the planner picks RB from the units a lane owns per row, so no load slot
+// idles).  When a whole row is one pass of the wave (no split, at most 64*KU
+// units), every lane sees the same units in every task, so its weights are
+// loaded once, before the task loop.  Each row sums into NA partial
+// accumulators (EU products fold into them in a fixed order).
+template <int RB>
+struct RowLongShape {
+  static constexpr int KU = 8 / RB;
+};
+
 template <int DT, bool VEC, int RB, int ROLE>
 __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Acc> a) {
   typedef typename St<DT>::Acc Acc;
   typedef Unit<DT, VEC> U;
   constexpr int EU = U::EU;
+  constexpr int KU = RowLongShape<RB>::KU;
+  constexpr int NA = EU < 4 ? EU : 4;
   const int lane = lane_id();
   const i64 ngroups = (a.L + RB - 1) / RB;
   const i64 ntasks = ngroups * a.nsplit;
-  const TaskRange tr = wave_tasks(ntasks);
+  const bool wreg = ROLE != kRoleRowWeights && a.nsplit == 1 && a.upr <= (i64)kWave * KU;
+  Acc wv[KU][EU];
+  if (wreg) {
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+      const i64 uk = lane + (i64)k * kWave;
+      if (uk < a.upr) {
+        load_w<Acc, EU>(a.w, uk * EU, wv[k]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < EU; ++e) wv[k][e] = (Acc)0;
+      }
+    }
+  }
+  const TaskRange tr = wave_tasks<true>(ntasks);
   for (i64 t = tr.begin; t < tr.end; t += tr.step) {
-    const i64 s = t / ngroups;
-    const i64 row0 = (t - s * ngroups) * RB;
+    i64 s, g;
+    divmod(t, ngroups, s, g);
+    const i64 row0 = g * RB;
     const i64 u0 = s * a.chunk;
     const i64 u1 = min(a.upr, u0 + a.chunk);
     const Acc* wr = a.w;
     if constexpr (ROLE == kRoleRowWeights) wr = a.w + (row0 / a.wdiv) * a.wstride;
-    Acc acc[RB][EU];
+    // uniform base of the chunk in each row; lanes add 32-bit byte offsets
+    // (the planner keeps a chunk below 2^31 bytes)
+    const char* cbase[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      cbase[r] = (const char*)a.A + ((row0 + r) * a.ld + u0 * EU) * (i64)sizeof(typename U::T);
+    Acc acc[RB][NA];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int e = 0; e < EU; ++e) acc[r][e] = (Acc)0;
-    for (i64 u = u0 + lane; u < u1; u += (i64)kWave * kUnroll) {
-      typename U::Raw raw[kUnroll][RB];
-      Acc wv[kUnroll][EU];
+      for (int e = 0; e < NA; ++e) acc[r][e] = (Acc)0;
+    for (i64 u = u0 + lane; u < u1; u += (i64)kWave * KU) {
+      typename U::Raw raw[KU][RB];
 #pragma unroll
-      for (int k = 0; k < kUnroll; ++k) {
+      for (int k = 0; k < KU; ++k) {
         const i64 uk = u + (i64)k * kWave;
         const bool ok = uk < u1;
+        const uint32_t off = (uint32_t)(uk - u0) * (uint32_t)(EU * sizeof(typename U::T));
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
           const i64 row = row0 + r;
-          raw[k][r] = (ok && row < a.L) ? U::load(a.A, row * a.upr + uk) : U::zero();
+          raw[k][r] = (ok && row < a.L) ? U::load(cbase[r] + (uint64_t)off, 0) : U::zero();
         }
-        if (ok) {
-          load_w<Acc, EU>(wr, uk * EU, wv[k]);
-        } else {
+        if (!wreg) {
+          if (ok) {
+            load_w<Acc, EU>(wr, uk * EU, wv[k]);
+          } else {
 #pragma unroll
-          for (int e = 0; e < EU; ++e) wv[k][e] = (Acc)0;
+            for (int e = 0; e < EU; ++e) wv[k][e] = (Acc)0;
+          }
         }
       }
 #pragma unroll
-      for (int k = 0; k < kUnroll; ++k)
+      for (int k = 0; k < KU; ++k)
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
           Acc v[EU];
           U::unpack(raw[k][r], v);
 #pragma unroll
-          for (int e = 0; e < EU; ++e) acc[r][e] = fma(v[e], wv[k][e], acc[r][e]);
+          for (int e = 0; e < EU; ++e) acc[r][e % NA] = fma(v[e], wv[k][e], acc[r][e % NA]);
         }
+    }
+    // Ragged row end (vector path): lane 0 reads the last EU elements of the
+    // row and skips the EU - tail of them that the last full unit covered.
+    if (a.tail > 0 && s == a.nsplit - 1 && lane == 0) {
+      const int from = EU - a.tail;
+      Acc wt[EU];
+      load_w<Acc, EU>(wr, a.ld - EU, wt);
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const i64 row = row0 + r;
+        if (row < a.L) {
+          Acc v[EU];
+          U::unpack(U::load(a.A, row * a.ld + a.ld - EU), v);
+#pragma unroll
+          for (int e = 0; e < EU; ++e)
+            if (e >= from) acc[r][e % NA] = fma(v[e], wt[e], acc[r][e % NA]);
+        }
+      }
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       Acc s_ = (Acc)0;
 #pragma unroll
-      for (int e = 0; e < EU; ++e) s_ += acc[r][e];
+      for (int e = 0; e < NA; ++e) s_ += acc[r][e];
       s_ = wave_sum(s_);
       const i64 row = row0 + r;
       if (lane == 0 && row < a.L) {
@@ -206,7 +257,9 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
 }
 
 // ---------------------------------------------------------------- kRow, short
-// G = 2^glog lanes per row (G >= units per row), 64/G rows per wave load.
+// G = 2^glog lanes per row (G >= units per row, a ragged end counting as one
+// more unit that re-reads the row's last EU elements and drops the overlap),
+// 64/G rows per wave load.
 template <int DT, bool VEC, int ROLE>
 __global__ __launch_bounds__(kBlock) void k_row_short(RowArgs<typename St<DT>::Acc> a) {
   typedef typename St<DT>::Acc Acc;
@@ -217,31 +270,38 @@ __global__ __launch_bounds__(kBlock) void k_row_short(RowArgs<typename St<DT>::A
   const int P = kWave >> a.glog;
   const int sub = lane & (G - 1);
   const int rsub = lane >> a.glog;
-  const bool active = sub < a.upr;
+  const bool tl = a.tail > 0 && sub == a.upr;
+  const bool active = sub < a.upr || tl;
+  const i64 eo = tl ? a.ld - EU : (i64)sub * EU;
+  const int from = tl ? EU - a.tail : 0;
   Acc wv[EU];
   if (active && ROLE != kRoleRowWeights) {
-    load_w<Acc, EU>(a.w, (i64)sub * EU, wv);
+    load_w<Acc, EU>(a.w, eo, wv);
   } else {
 #pragma unroll
     for (int e = 0; e < EU; ++e) wv[e] = (Acc)0;
   }
   const i64 per = (i64)P * kShortUnroll;
-  const TaskRange tr = wave_tasks((a.L + per - 1) / per);
+  const TaskRange tr = wave_tasks<false>((a.L + per - 1) / per);
   for (i64 t = tr.begin; t < tr.end; t += tr.step) {
     const i64 base = t * per;
     typename U::Raw raw[kShortUnroll];
 #pragma unroll
     for (int k = 0; k < kShortUnroll; ++k) {
       const i64 row = base + (i64)k * P + rsub;
-      raw[k] = (active && row < a.L) ? U::load(a.A, row * a.upr + sub) : U::zero();
+      raw[k] = (active && row < a.L) ? U::load(a.A, row * a.ld + eo) : U::zero();
     }
 #pragma unroll
     for (int k = 0; k < kShortUnroll; ++k) {
       Acc v[EU];
       U::unpack(raw[k], v);
+      if (a.tail > 0) {
+#pragma unroll
+        for (int e = 0; e < EU; ++e) v[e] = e < from ? (Acc)0 : v[e];
+      }
       if constexpr (ROLE == kRoleRowWeights) {
         const i64 row = base + (i64)k * P + rsub;
-        if (active && row < a.L) load_w<Acc, EU>(a.w + (row / a.wdiv) * a.wstride, (i64)sub * EU, wv);
+        if (active && row < a.L) load_w<Acc, EU>(a.w + (row / a.wdiv) * a.wstride, eo, wv);
       }
       Acc s_ = (Acc)0;
 #pragma unroll
@@ -257,7 +317,9 @@ __global__ __launch_bounds__(kBlock) void k_row_short(RowArgs<typename St<DT>::A
 // ---------------------------------------------------------------- kCol
 // Workgroup task = (split s, slab l, column tile ct), ct fastest.  TC threads
 // along columns (one unit each), SPLITM wave groups along the rows, each
-// keeping UN loads in flight; the groups combine in LDS.
+// keeping UN loads in flight; the groups combine in LDS.  A ragged row end
+// is one more unit reading the last EU columns; it stores only the columns
+// after the last full unit.
 template <int DT, bool VEC, int SPLITM, int ROLE>
 __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a) {
   typedef typename St<DT>::Acc Acc;
@@ -271,12 +333,13 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a)
   const i64 ntasks = a.L * a.ctiles * a.nsplit;
   const TaskRange tr = block_tasks(ntasks);
   for (i64 t = tr.begin; t < tr.end; t += tr.step) {
-    const i64 ct = t % a.ctiles;
-    const i64 rest = t / a.ctiles;
-    const i64 l = rest % a.L;
-    const i64 s = rest / a.L;
+    i64 ct, rest, l, s;
+    divmod(t, a.ctiles, rest, ct);
+    divmod(rest, a.L, s, l);
     const i64 c = ct * TC + tc;
-    const bool active = c < a.upr;
+    const bool tl = a.tail > 0 && c == a.upr;
+    const bool active = c < a.upr || tl;
+    const i64 eo = tl ? a.R - EU : c * EU;
     const i64 m0 = s * a.chunk;
     const i64 m1 = min(a.M, m0 + a.chunk);
     const i64 slab = l * a.M;
@@ -290,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a)
       for (int k = 0; k < UN; ++k) {
         const i64 mk = m + (i64)k * SPLITM;
         const bool ok = mk < m1;
-        raw[k] = (active && ok) ? U::load(a.A, (slab + mk) * a.upr + c) : U::zero();
+        raw[k] = (active && ok) ? U::load(a.A, (slab + mk) * a.R + eo) : U::zero();
         wv[k] = ok ? a.w[mk] : (Acc)0;
       }
 #pragma unroll
@@ -315,9 +378,10 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a)
       }
     }
     if (grp == 0 && active) {
-      const i64 idx = l * a.R + c * EU;
-      if (a.nsplit > 1) store_units<Acc, EU, VEC>(a.part + s * (a.L * a.R) + idx, acc, a.y16);
-      else store_epilogue<Acc, EU, VEC>(acc, a.y, idx, l, a.alpha, a.beta, a.oscale, a.odiv, a.y16);
+      const i64 idx = l * a.R + eo;
+      const int from = tl ? EU - a.tail : 0;
+      if (a.nsplit > 1) store_units<Acc, EU>(a.part + s * (a.L * a.R) + idx, acc, from);
+      else store_epilogue<Acc, EU>(acc, a.y, idx, l, a.alpha, a.beta, a.oscale, a.odiv, from);
     }
     if constexpr (SPLITM > 1) __syncthreads();
   }
@@ -329,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a)
 // l0 + q and streams down the M rows of that slab, so no cross-lane
 // reduction is needed; for a fixed row a wave load reads P contiguous
 // segments of G*16 bytes, one per slab.  The weight of a row is uniform
-// across the wave.
+// across the wave.  A ragged row end is handled as in kCol.
 template <int DT, bool VEC, int ROLE>
 __global__ __launch_bounds__(kBlock) void k_slab(ColArgs<typename St<DT>::Acc> a) {
   typedef typename St<DT>::Acc Acc;
@@ -343,15 +407,17 @@ __global__ __launch_bounds__(kBlock) void k_slab(ColArgs<typename St<DT>::Acc> a
   const int c = lane & (G - 1);
   const i64 groups = (a.L + P - 1) / P;
   const i64 ntasks = groups * a.nsplit;
-  const TaskRange tr = wave_tasks(ntasks);
+  const TaskRange tr = wave_tasks<false>(ntasks);
   for (i64 t = tr.begin; t < tr.end; t += tr.step) {
-    const i64 g = t % groups;
-    const i64 s = t / groups;
+    i64 g, s;
+    divmod(t, groups, s, g);
     const i64 l = g * P + q;
-    const bool on = c < a.upr && l < a.L;
+    const bool tl = a.tail > 0 && c == a.upr;
+    const bool on = (c < a.upr || tl) && l < a.L;
+    const i64 eo = tl ? a.R - EU : (i64)c * EU;
     const i64 m0 = s * a.chunk;
     const i64 m1 = min(a.M, m0 + a.chunk);
-    const i64 base = l * a.M * a.upr + c;
+    const i64 base = l * a.M * a.R + eo;
     Acc acc[EU];
 #pragma unroll
     for (int e = 0; e < EU; ++e) acc[e] = (Acc)0;
@@ -362,7 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_slab(ColArgs<typename St<DT>::Acc> a
       for (int k = 0; k < UN; ++k) {
         const i64 mk = m + k;
         const bool ok = mk < m1;
-        raw[k] = (on && ok) ? U::load(a.A, base + mk * a.upr) : U::zero();
+        raw[k] = (on && ok) ? U::load(a.A, base + mk * a.R) : U::zero();
         wv[k] = ok ? a.w[mk] : (Acc)0;
       }
 #pragma unroll
@@ -374,9 +440,97 @@ __global__ __launch_bounds__(kBlock) void k_slab(ColArgs<typename St<DT>::Acc> a
       }
     }
     if (on) {
-      const i64 idx = l * a.R + (i64)c * EU;
-      if (a.nsplit > 1) store_units<Acc, EU, VEC>(a.part + s * (a.L * a.R) + idx, acc, a.y16);
-      else store_epilogue<Acc, EU, VEC>(acc, a.y, idx, l, a.alpha, a.beta, a.oscale, a.odiv, a.y16);
+      const i64 idx = l * a.R + eo;
+      const int from = tl ? EU - a.tail : 0;
+      if (a.nsplit > 1) store_units<Acc, EU>(a.part + s * (a.L * a.R) + idx, acc, from);
+      else store_epilogue<Acc, EU>(acc, a.y, idx, l, a.alpha, a.beta, a.oscale, a.odiv, from);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- kStage
+// A slab l is the contiguous block A[l][0..M)[0..R) of E = M*R elements.  A
+// workgroup takes blocks of sb consecutive slabs (sb*E elements, a multiple
+// of 16 bytes, so every block starts 16-byte aligned): it copies a block
+// into LDS with 16-byte loads, each thread holding kStageVecs/256 of them,
+// issues the loads of its next block, and computes the current block's
+// sb*R outputs from LDS while those loads are in flight.  G = 2^glog lanes
+// per output split the contracted extent and combine with shuffles.
+constexpr int kStageBytes = 32768;
+constexpr int kStageVecs = kStageBytes / 16;
+constexpr int kStagePer = kStageVecs / kBlock;
+
+template <typename Acc>
+struct StageArgs {
+  const void* A; const Acc* w; Acc* y;
+  i64 L, M, R, sb, nblocks;
+  int glog;
+  Acc alpha, beta;
+  const float* oscale; i64 odiv;
+};
+
+template <int DT, int ROLE>
+__global__ __launch_bounds__(kBlock) void k_stage(StageArgs<typename St<DT>::Acc> a) {
+  typedef typename St<DT>::Acc Acc;
+  typedef typename St<DT>::T T;
+  constexpr int EB = (int)sizeof(T);
+  __shared__ uint4 lds[kStageVecs];
+  const int tid = threadIdx.x;
+  const i64 E = a.M * a.R;
+  const int G = 1 << a.glog;
+  const int sub = tid & (G - 1);
+  uint4 r[kStagePer];
+  i64 nvec = 0;
+  auto issue = [&](i64 b) {
+    const i64 l0 = b * a.sb;
+    const i64 ns = min(a.sb, a.L - l0);
+    nvec = ns * E * EB / 16;
+    const char* src = (const char*)a.A + l0 * E * EB;
+#pragma unroll
+    for (int k = 0; k < kStagePer; ++k) {
+      const i64 v = tid + (i64)k * kBlock;
+      r[k] = v < nvec ? stream_load16(src + v * 16) : uint4{0u, 0u, 0u, 0u};
+    }
+  };
+  i64 b = blockIdx.x;
+  if (b < a.nblocks) issue(b);
+  for (; b < a.nblocks; b += gridDim.x) {
+    const i64 l0 = b * a.sb;
+    const i64 ns = min(a.sb, a.L - l0);
+    __syncthreads();  // the previous block's outputs no longer read the LDS
+#pragma unroll
+    for (int k = 0; k < kStagePer; ++k) {
+      const i64 v = tid + (i64)k * kBlock;
+      if (v < nvec) lds[v] = r[k];
+    }
+    {  // bytes of the last block after its final whole 16-byte vector
+      const i64 e0 = nvec * 16 / EB, e1 = ns * E;
+      const T* src = (const T*)a.A + l0 * E;
+      if (e0 + tid < e1) ((T*)lds)[e0 + tid] = src[e0 + tid];
+    }
+    __syncthreads();
+    if (b + gridDim.x < a.nblocks) issue(b + gridDim.x);
+    const i64 nout = ns * a.R;
+    const T* sl = (const T*)lds;
+    for (i64 o = tid >> a.glog; o < a.sb * a.R; o += kBlock >> a.glog) {
+      Acc acc0 = (Acc)0, acc1 = (Acc)0;
+      i64 ls, rr;
+      divmod(o, a.R, ls, rr);
+      if (o < nout) {
+        const i64 base = ls * E + rr;
+        i64 m = sub;
+        for (; m + G < a.M; m += 2 * G) {
+          acc0 = fma(load_elem<DT>(sl, base + m * a.R), a.w[m], acc0);
+          acc1 = fma(load_elem<DT>(sl, base + (m + G) * a.R), a.w[m + G], acc1);
+        }
+        if (m < a.M) acc0 = fma(load_elem<DT>(sl, base + m * a.R), a.w[m], acc0);
+      }
+      Acc v = acc0 + acc1;
+      for (int off = G >> 1; off >= 1; off >>= 1) v += shfl_xor(v, off);
+      if (sub == 0 && o < nout) {
+        const i64 idx = l0 * a.R + o;
+        a.y[idx] = epilogue(v, a.y, idx, l0 + ls, a.alpha, a.beta, a.oscale, a.odiv);
+      }
     }
   }
 }
@@ -469,54 +623,109 @@ int grid_for(i64 blocks_needed, int family, int default_bpc) {
 
 }  // namespace
 
-TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a16, bool w16) {
+namespace {
+
+i64 gcd_(i64 a, i64 b) {
+  while (b) {
+    const i64 t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+}  // namespace
+
+TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
   TvcPlan p;
   const i64 b = (i64)elem_bytes(dtype);
   const i64 epv = 16 / b;
   const size_t ab = acc_bytes(dtype);
   const int waves_per_block = kBlock / kWave;
+  // 16-byte units need every row of the contiguous extent to start on a
+  // dword boundary and to hold at least one unit; a ragged end (len mod EPV
+  // elements) is one more unit.
+  const i64 len = R == 1 ? M : R;
+  p.vec = a4 && (R != 1 || w4) && (len * b) % 4 == 0 && len >= epv;
+  p.upr = p.vec ? len / epv : len;
+  p.tail = p.vec ? (int)(len % epv) : 0;
+  const i64 nu = p.upr + (p.tail > 0 ? 1 : 0);
+  // Small slabs: stage whole slabs through LDS where the row and slab
+  // kernels lose coalescing (measured on gfx950 over the Table 1 shapes):
+  // rows of 33-64 units (a wave per row, too short to stream), and slabs of
+  // at most 4 KB whose right extent is ragged, not a power of two, or at
+  // most 2 units wide.  Short rows (<= 32 units) and power-of-two slab
+  // widths stay with their own kernels, which are faster there.  A block of
+  // sb slabs must be a multiple of 16 bytes.
+  const i64 sbytes = M * R * b;
+  const bool pow2 = (nu & (nu - 1)) == 0;
+  const bool small = R == 1 ? (p.vec && nu > 32 && nu <= 64)
+                            : (sbytes <= 4096 && nu <= 32 && (p.tail > 0 || !pow2 || nu <= 2));
+  if (a16 && small && !tuning().stage_off) {
+    const i64 q = 16 / gcd_(16, sbytes);
+    const i64 sb = (kStageBytes / sbytes) / q * q;
+    if (sb >= 1) {
+      p.family = kStage;
+      p.sb = sb;
+      p.vec = true;
+      // lanes per output: as many as keep all 256 threads busy (measured:
+      // a whole wave per row serialises the row reductions and is slower)
+      const i64 outs = std::max<i64>(sb * R, 1);
+      int g = 0;
+      while (g < 6 && ((i64)2 << g) * outs <= kBlock && ((i64)1 << g) < M) ++g;
+      p.glog = g;
+      p.nsplit = 1;
+      p.tasks = cdiv(L, sb);
+      p.grid = grid_for(p.tasks, kStage, 4);
+      p.part_bytes = 0;
+      return p;
+    }
+  }
   if (R == 1) {
     p.family = kRow;
-    p.vec = a16 && w16 && (M * b) % 16 == 0;
-    const i64 eu = p.vec ? epv : 1;
-    p.upr = M / eu;
-    if (p.upr > 32) {
+    if (nu > 32) {
       p.lng = true;
-      // rows sharing one weight load: enough that a lane keeps 8 loads in flight
-      p.rb = L >= 4 && p.upr <= 2 * kWave ? 4 : (L >= 2 ? 2 : 1);
+      // rows sharing one weight load: RB rows x 8/RB units per lane keeps 8
+      // loads in flight (units per lane per row: ceil(upr / 64))
+      const i64 q = cdiv(p.upr, kWave);
+      p.rb = L >= 8 && q <= 1 ? 8 : (L >= 4 && q <= 3 ? 4 : (L >= 2 ? 2 : 1));
       const i64 groups = cdiv(L, p.rb);
       p.nsplit = 1;
       p.chunk = p.upr;
+      // lanes address a chunk with 32-bit byte offsets: at most 2^31 bytes
+      const i64 max_chunk = ((i64)1 << 31) / (p.vec ? 16 : b);
       // Few long rows: split each row so that enough waves stream at once.
       const i64 want = 8 * (i64)device_cus();
-      if (groups < want && p.upr >= 2 * kWave * kUnroll) {
-        i64 ns = std::min<i64>(cdiv(2 * want, groups), p.upr / (kWave * kUnroll));
+      const i64 ku = 8 / p.rb;
+      if (groups < want && p.upr >= 2 * kWave * ku) {
+        i64 ns = std::min<i64>(cdiv(2 * want, groups), p.upr / (kWave * ku));
         ns = std::max<i64>(ns, 1);
         i64 chunk = cdiv(p.upr, ns);
         chunk = cdiv(chunk, kWave) * kWave;
         p.chunk = chunk;
         p.nsplit = (int)cdiv(p.upr, chunk);
       }
+      if (p.chunk > max_chunk) {
+        p.chunk = max_chunk;  // a multiple of the wave width
+        p.nsplit = (int)cdiv(p.upr, p.chunk);
+      }
       p.tasks = groups * p.nsplit;
       p.grid = grid_for(cdiv(p.tasks, waves_per_block), kRow, 16);
     } else {
       p.lng = false;
-      p.glog = ceil_log2(std::max<i64>(p.upr, 1));
+      p.glog = ceil_log2(std::max<i64>(nu, 1));
       const i64 per = (i64)(kWave >> p.glog) * kShortUnroll;
       p.tasks = cdiv(L, per);
       p.grid = grid_for(cdiv(p.tasks, waves_per_block), kRow, 4);
     }
   } else {
-    p.vec = a16 && (R * b) % 16 == 0;
-    const i64 eu = p.vec ? epv : 1;
-    p.upr = R / eu;
-    if (p.upr > 32) {
+    if (nu > 32) {
       p.family = kCol;
       int sm = tuning().split_m > 0 ? tuning().split_m : (M >= 8 ? 4 : 1);
       if (sm != 1 && sm != 2 && sm != 4) sm = 4;
       p.splitm = sm;
       const i64 tc = kBlock / sm;
-      const i64 ctiles = cdiv(p.upr, tc);
+      const i64 ctiles = cdiv(nu, tc);
       const i64 tasks = L * ctiles;
       p.nsplit = 1;
       p.chunk = M;
@@ -531,7 +740,7 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a16, bool w16) {
       p.grid = grid_for(p.tasks, kCol, 4);
     } else {
       p.family = kSlab;
-      p.glog = ceil_log2(std::max<i64>(p.upr, 1));
+      p.glog = ceil_log2(std::max<i64>(nu, 1));
       const i64 P = kWave >> p.glog;
       const i64 groups = cdiv(L, P);
       p.nsplit = 1;
@@ -563,16 +772,23 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
   Acc* part = (Acc*)part_;
   const dim3 blk(kBlock);
   const dim3 grd(p.grid);
+  if (p.family == kStage) {
+    StageArgs<Acc> a{A, w, y, L, M, R, p.sb, p.tasks, p.glog, (Acc)alpha, (Acc)beta, oscale, odiv};
+    hipLaunchKernelGGL((k_stage<DT, ROLE>), grd, blk, 0, st, a);
+    return hipGetLastError();
+  }
   if (p.family == kRow) {
     RowArgs<Acc> a{A, w, y, part, L, p.upr, p.chunk, p.nsplit, p.glog, (Acc)alpha, (Acc)beta,
-                   oscale, odiv, 1, 0};
+                   oscale, odiv, 1, 0, M, p.tail};
     if (p.lng) {
       if (p.vec) {
-        if (p.rb == 4) hipLaunchKernelGGL((k_row_long<DT, true, 4, ROLE>), grd, blk, 0, st, a);
+        if (p.rb == 8) hipLaunchKernelGGL((k_row_long<DT, true, 8, ROLE>), grd, blk, 0, st, a);
+        else if (p.rb == 4) hipLaunchKernelGGL((k_row_long<DT, true, 4, ROLE>), grd, blk, 0, st, a);
         else if (p.rb == 2) hipLaunchKernelGGL((k_row_long<DT, true, 2, ROLE>), grd, blk, 0, st, a);
         else hipLaunchKernelGGL((k_row_long<DT, true, 1, ROLE>), grd, blk, 0, st, a);
       } else {
-        if (p.rb == 4) hipLaunchKernelGGL((k_row_long<DT, false, 4, ROLE>), grd, blk, 0, st, a);
+        if (p.rb == 8) hipLaunchKernelGGL((k_row_long<DT, false, 8, ROLE>), grd, blk, 0, st, a);
+        else if (p.rb == 4) hipLaunchKernelGGL((k_row_long<DT, false, 4, ROLE>), grd, blk, 0, st, a);
         else if (p.rb == 2) hipLaunchKernelGGL((k_row_long<DT, false, 2, ROLE>), grd, blk, 0, st, a);
         else hipLaunchKernelGGL((k_row_long<DT, false, 1, ROLE>), grd, blk, 0, st, a);
       }
@@ -582,9 +798,9 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
     }
   } else {
     const i64 tc = kBlock / p.splitm;
-    const int y16 = ((uintptr_t)y % 16 == 0) ? 1 : 0;
-    ColArgs<Acc> a{A, w, y, part, L, M, p.upr, R, (p.upr + tc - 1) / tc, p.chunk, p.nsplit,
-                   p.glog, (Acc)alpha, (Acc)beta, oscale, odiv, y16};
+    const i64 nu = p.upr + (p.tail > 0 ? 1 : 0);
+    ColArgs<Acc> a{A, w, y, part, L, M, p.upr, R, (nu + tc - 1) / tc, p.chunk, p.nsplit,
+                   p.glog, (Acc)alpha, (Acc)beta, oscale, odiv, p.tail};
     if (p.family == kCol) {
       if (p.vec) {
         if (p.splitm == 4) hipLaunchKernelGGL((k_col<DT, true, 4, ROLE>), grd, blk, 0, st, a);
@@ -620,12 +836,21 @@ hipError_t run_rows_pw_dt(const void* A, i64 L, i64 M, const void* w_, i64 wdiv,
                           hipStream_t st) {
   typedef typename St<DT>::Acc Acc;
   RowArgs<Acc> a{A, (const Acc*)w_, (Acc*)y_, (Acc*)part_, L, p.upr, p.chunk, p.nsplit, p.glog,
-                 (Acc)1, (Acc)0, oscale, odiv, wdiv, wstride};
+                 (Acc)1, (Acc)0, oscale, odiv, wdiv, wstride, M, p.tail};
   const dim3 blk(kBlock), grd(p.grid);
   constexpr int RW = kRoleRowWeights;
   if (p.lng) {
-    if (p.vec) hipLaunchKernelGGL((k_row_long<DT, true, 1, RW>), grd, blk, 0, st, a);
-    else hipLaunchKernelGGL((k_row_long<DT, false, 1, RW>), grd, blk, 0, st, a);
+    if (p.vec) {
+      if (p.rb == 8) hipLaunchKernelGGL((k_row_long<DT, true, 8, RW>), grd, blk, 0, st, a);
+      else if (p.rb == 4) hipLaunchKernelGGL((k_row_long<DT, true, 4, RW>), grd, blk, 0, st, a);
+      else if (p.rb == 2) hipLaunchKernelGGL((k_row_long<DT, true, 2, RW>), grd, blk, 0, st, a);
+      else hipLaunchKernelGGL((k_row_long<DT, true, 1, RW>), grd, blk, 0, st, a);
+    } else {
+      if (p.rb == 8) hipLaunchKernelGGL((k_row_long<DT, false, 8, RW>), grd, blk, 0, st, a);
+      else if (p.rb == 4) hipLaunchKernelGGL((k_row_long<DT, false, 4, RW>), grd, blk, 0, st, a);
+      else if (p.rb == 2) hipLaunchKernelGGL((k_row_long<DT, false, 2, RW>), grd, blk, 0, st, a);
+      else hipLaunchKernelGGL((k_row_long<DT, false, 1, RW>), grd, blk, 0, st, a);
+    }
   } else {
     if (p.vec) hipLaunchKernelGGL((k_row_short<DT, true, RW>), grd, blk, 0, st, a);
     else hipLaunchKernelGGL((k_row_short<DT, false, RW>), grd, blk, 0, st, a);
@@ -638,13 +863,18 @@ hipError_t run_rows_pw_dt(const void* A, i64 L, i64 M, const void* w_, i64 wdiv,
 
 }  // namespace
 
-TvcPlan plan_rows_pw(int dtype, i64 L, i64 M, bool a16, bool w16) {
-  TvcPlan p = plan_tvc(dtype, L, M, 1, a16, w16);
-  if (p.lng && p.rb != 1) {
-    p.rb = 1;
-    const i64 groups = L;
-    p.tasks = groups * p.nsplit;
-    p.grid = grid_for(cdiv(p.tasks, kBlock / kWave), kRow, 8);
+TvcPlan plan_rows_pw(int dtype, i64 L, i64 M, bool a4, bool w4, i64 wdiv) {
+  TvcPlan p = plan_tvc(dtype, L, M, 1, a4, w4, false);
+  if (p.lng) {
+    // RB rows of a wave share one weight row: RB must divide wdiv (row
+    // groups start at multiples of RB)
+    int rb = p.rb;
+    while (rb > 1 && (wdiv % rb) != 0) rb /= 2;
+    if (rb != p.rb) {
+      p.rb = rb;
+      p.tasks = cdiv(L, rb) * p.nsplit;
+      p.grid = grid_for(cdiv(p.tasks, kBlock / kWave), kRow, 16);
+    }
   }
   return p;
 }
@@ -683,9 +913,10 @@ hipError_t run_tvc(int dtype, const void* A, i64 L, i64 M, i64 R, const void* w,
 tvc_status tvc_run_auto(int dtype, const void* A, i64 L, i64 M, i64 R, const void* w, void* y,
                         double alpha, double beta, const float* oscale, i64 odiv, void* ws,
                         size_t ws_bytes, hipStream_t st, int role) {
+  const bool a4 = ((uintptr_t)A % 4) == 0;
+  const bool w4 = ((uintptr_t)w % 4) == 0;
   const bool a16 = ((uintptr_t)A % 16) == 0;
-  const bool w16 = ((uintptr_t)w % 16) == 0;
-  TvcPlan p = plan_tvc(dtype, L, M, R, a16, w16);
+  TvcPlan p = plan_tvc(dtype, L, M, R, a4, w4, a16);
   if (p.part_bytes > ws_bytes || (p.part_bytes > 0 && ws == nullptr))
     return fail(TVC_EWORKSPACE, "internal contraction needs " + std::to_string(p.part_bytes) +
                                     " workspace bytes");

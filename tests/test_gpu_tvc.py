@@ -107,7 +107,106 @@ def test_bitwise_deterministic(dev, dims):
         assert torch.equal(a, b)
 
 
-def test_misaligned_vector_falls_back(dev):
+# Contiguous rows that start on a 4-byte boundary but are not whole 16-byte
+# vectors: the vector path with a ragged row end, in every family and with
+# split contracted extents.  Lengths per format keep rows dword-aligned.
+EPV = {"f64": 2, "f32": 4, "f16": 8, "bf16": 8, "e4m3": 16}
+RAGGED_LEN = {"f64": (1001, 13, 200001), "f32": (1001, 13, 200001), "f16": (1002, 14, 200002),
+              "bf16": (1002, 14, 200002), "e4m3": (1004, 20, 200004)}
+
+
+def _ragged_cases(fmt):
+    lg, sh, huge = RAGGED_LEN[fmt]
+    return [
+        ((37, lg), 1, "row"),           # long rows
+        ((37, lg), 0, "col"),           # column streaming
+        ((3000, lg), 0, "col"),         # column streaming, split contracted extent
+        ((300, sh), 1, "row"),          # short rows, several per wave
+        ((300, sh), 0, "slab"),         # one slab
+        ((50, 60, sh), 1, "slab"),      # many slabs
+        ((3, 5000, sh), 1, "slab"),     # few slabs, split contracted extent
+        ((huge,), 0, "row"),            # one long row split across workgroups
+        ((2, 3, lg), 2, "row"),
+    ]
+
+
+@pytest.fixture
+def no_stage():
+    # the small-slab shapes below would go to the LDS-staged family; turn it
+    # off so the row and slab kernels' ragged paths are the ones tested
+    from paper_2501_03121_amd import tune
+    tune.set_tuning("stage", -1)
+    yield
+    tune.set_tuning("stage", 0)
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_ragged_vector_rows(dev, fmt, no_stage):
+    for dims, k, family in _ragged_cases(fmt):
+        A, S, exact = stored_tensor(dims, fmt, 13, dev)
+        p = tvc.contract_plan(A, k, scale=S)
+        contiguous = int(np.prod(dims[k + 1:])) if k + 1 < len(dims) else dims[k]
+        assert p["family"] == family and p["vec"], (fmt, dims, k, p)
+        assert p["tail"] == contiguous % EPV[fmt] and p["tail"] > 0, (fmt, dims, k, p)
+        x, xh = vec(dims[k], 70 + k, fmt, dev)
+        for alpha, beta in ((1.0, 0.0), (0.5, -2.0)):
+            y0 = torch.from_numpy(synth.uniform(O.output_dims(dims, k), 80 + k))
+            y0 = y0.to(torch.float64 if fmt == "f64" else torch.float32)
+            out = y0.to(dev)
+            tvc.contract(A, x, k, alpha=alpha, beta=beta, out=out, scale=S)
+            ref = O.tvc(exact, xh, k, alpha=alpha, beta=beta, y=host(y0))
+            err = O.rel_err(host(out), ref)
+            assert err <= TOL[fmt], (fmt, dims, k, alpha, beta, err)
+
+
+# Small slabs staged through LDS in blocks of whole slabs: rows of 33-64
+# 16-byte units, and slabs of at most 4 KB with a ragged, non-power-of-two or
+# very narrow right extent.  The cases cover a single partial block, a ragged
+# last block, one-element right extents and several blocks per workgroup.
+def _staged_cases(fmt):
+    rl = 45 * EPV[fmt] + {"f64": 1, "f32": 1, "f16": 2, "bf16": 2, "e4m3": 4}[fmt]
+    return [((3000, rl), 1), ((7, 11, rl), 2), ((13,) * 5, 3), ((50, 37, 13), 1),
+            ((1001, 3, 7), 1), ((9, 15, 31), 1), ((3, 5, 7), 1), ((6, 7, 1, 9), 2),
+            ((2, 3, 4, 5, 6, 7), 4)]
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_staged_small_slabs(dev, fmt):
+    for dims, k in _staged_cases(fmt):
+        A, S, exact = stored_tensor(dims, fmt, 17, dev)
+        p = tvc.contract_plan(A, k, scale=S)
+        assert p["family"] == "stage", (fmt, dims, k, p)
+        x, xh = vec(dims[k], 90 + k, fmt, dev)
+        for alpha, beta in ((1.0, 0.0), (-1.5, 0.25)):
+            y0 = torch.from_numpy(synth.uniform(O.output_dims(dims, k), 95 + k))
+            y0 = y0.to(torch.float64 if fmt == "f64" else torch.float32)
+            out = y0.to(dev)
+            tvc.contract(A, x, k, alpha=alpha, beta=beta, out=out, scale=S)
+            ref = O.tvc(exact, xh, k, alpha=alpha, beta=beta, y=host(y0))
+            err = O.rel_err(host(out), ref)
+            assert err <= TOL[fmt], (fmt, dims, k, alpha, beta, err)
+
+
+def test_staged_equals_unstaged_bitwise_on_integers(dev):
+    # exact sums: the staged and the row/slab kernels agree bit for bit
+    from paper_2501_03121_amd import tune
+    for dims, k in _staged_cases("f32")[:6]:
+        base = synth.integers(dims, 21, -8, 8)
+        A = torch.from_numpy(base).float().to(dev)
+        xh = synth.integers(dims[k], 22, -4, 4)
+        x = torch.from_numpy(xh).float().to(dev)
+        a = tvc.contract(A, x, k).clone()
+        tune.set_tuning("stage", -1)
+        try:
+            assert tvc.contract_plan(A, k)["family"] != "stage"
+            b = tvc.contract(A, x, k)
+        finally:
+            tune.set_tuning("stage", 0)
+        assert torch.equal(a, b)
+        assert np.array_equal(host(a), O.tvc(base, xh, k))
+
+
+def test_weights_at_4_byte_offset(dev):
     dims = (40, 256)
     A, _, exact = stored_tensor(dims, "f32", 11, dev)
     big = torch.zeros(257, dtype=torch.float32, device=dev)
