@@ -241,17 +241,37 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
         }
       }
     }
+    // Cross-lane reduction of the RB row sums as a butterfly: each of the
+    // first log2(RB) exchanges hands half of a lane's rows to its partner,
+    // so a lane ends with one row's partial sum (row rsel) after RB - 1
+    // shuffles instead of RB * 6; the rest is a plain xor reduction among
+    // the 64/RB lanes holding that row.
+    Acc v[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      Acc s_ = (Acc)0;
+      v[r] = (Acc)0;
 #pragma unroll
-      for (int e = 0; e < NA; ++e) s_ += acc[r][e];
-      s_ = wave_sum(s_);
-      const i64 row = row0 + r;
-      if (lane == 0 && row < a.L) {
-        if (a.nsplit > 1) a.part[s * a.L + row] = s_;
-        else a.y[row] = epilogue(s_, a.y, row, row, a.alpha, a.beta, a.oscale, a.odiv);
+      for (int e = 0; e < NA; ++e) v[r] += acc[r][e];
+    }
+    int rsel = 0;
+#pragma unroll
+    for (int h = RB / 2, off = kWave / 2; h >= 1; h /= 2, off /= 2) {
+      const bool up = (lane & off) != 0;
+#pragma unroll
+      for (int i = 0; i < h; ++i) {
+        const Acc keep = up ? v[i + h] : v[i];
+        const Acc send = up ? v[i] : v[i + h];
+        v[i] = keep + shfl_xor(send, off);
       }
+      rsel += up ? h : 0;
+    }
+    Acc s_ = v[0];
+#pragma unroll
+    for (int off = kWave / (2 * RB); off >= 1; off /= 2) s_ += shfl_xor(s_, off);
+    const i64 row = row0 + rsel;
+    if ((lane & (kWave / RB - 1)) == 0 && row < a.L) {
+      if (a.nsplit > 1) a.part[s * a.L + row] = s_;
+      else a.y[row] = epilogue(s_, a.y, row, row, a.alpha, a.beta, a.oscale, a.odiv);
     }
   }
 }
