@@ -505,7 +505,7 @@ def run_batch(dev, count: int = 512, sweeps: int = 50):
             x.copy_(v)
 
     total = sum(A.numel() for A in As)
-    te, grid, table = B.autotune(As, xs, sweeps, reset, tile_choices=(1 << 14, 1 << 16, 1 << 18),
+    te, grid, table = B.autotune(As, xs, sweeps, reset, tile_choices=(1 << 18, 1 << 19, 1 << 20),
                                  grid_per_cu=(4, 8), reps=1)
     bp = B.prepare(As, xs, sweeps, tile_elems=te, grid=grid)
     g = B.capture(bp, reset)
