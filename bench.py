@@ -518,12 +518,14 @@ def run_batch(dev, count: int = 512, sweeps: int = 50):
         times.append(time.perf_counter() - t0)
     err = B.error_word(bp)
     res = B.results(bp)
+    prof = B.profile(bp)
     t = min(times)
     nbytes = 2 * total * 4 * sweeps
     out = {"instances": count, "sweeps": sweeps, "elements": total, "tensor_GB": round(total * 4 / 1e9, 3),
            "seconds": round(t, 4), "GBps": round(nbytes / t / 1e9, 1),
            "pct_peak": round(100 * nbytes / t / 1e9 / PEAK_HBM_GBS, 1), "tile_elems": te, "grid": grid,
            "error_word": err, "degenerate": sum(r.status != 0 for r in res),
+           "work_items": prof["items"], "grid_busy_fraction": round(prof["busy_fraction"], 3),
            "autotune": table}
     log(json.dumps({k: v for k, v in out.items() if k != "autotune"}))
     return out

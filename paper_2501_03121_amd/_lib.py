@@ -114,6 +114,7 @@ SIGNATURES = {
     "hopm_batch_prepare": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p]),
     "hopm_batch_run": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p, c_void_p]),
     "hopm_batch_error": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "hopm_batch_profile": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "tvc_set_tuning": (c_int32, [c_int32, c_int32, c_int32]),
     "tvc_probe_read": (c_int32, [c_void_p, c_size_t, c_void_p, c_int32, c_void_p]),
     "tvc_probe_copy": (c_int32, [c_void_p, c_void_p, c_size_t, c_int32, c_void_p]),

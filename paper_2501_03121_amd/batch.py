@@ -95,6 +95,18 @@ def error_word(bp: BatchPlan) -> int:
     return int(bp.err.item())
 
 
+def profile(bp: BatchPlan) -> dict:
+    """Work items run and the persistent grid's time split (seconds summed
+    over workgroups) between waiting for queue slots and running items, for
+    the last run on this plan's workspace."""
+    out = torch.zeros(3, dtype=torch.int64, device=bp.ws.device)
+    s = torch.cuda.current_stream().cuda_stream
+    L.check(L.lib().hopm_batch_profile(_ws_ptr(bp), out.data_ptr(), s))
+    items, wait, work = (int(v) for v in out.cpu().tolist())
+    return {"items": items, "wait_s": wait / 1e8, "work_s": work / 1e8,
+            "busy_fraction": work / max(wait + work, 1)}
+
+
 def results(bp: BatchPlan) -> list:
     """Per-instance HopmResult in the caller's instance order."""
     raw = bp.stats.cpu().numpy().tobytes()

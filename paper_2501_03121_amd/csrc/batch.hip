@@ -55,6 +55,8 @@ struct BatchHeader {
   uint32_t tail;
   uint32_t done;
   uint32_t error;
+  // profile of the last run (wall clock ticks summed over workgroups)
+  unsigned long long items, wait_ticks, work_ticks;
 };
 
 constexpr int kBThreads = 256;
@@ -270,7 +272,7 @@ __device__ void phase_p1(const BatchDesc& D, const InstLayout& L, float* s, int 
     }
     return;
   }
-  constexpr int RU = 4;  // row groups in flight per wave
+  constexpr int RU = 8;  // row groups in flight per wave
   constexpr int NW = kBThreads / kWave;
   const int64_t U = R / 4;
   const int T = (int)(R % 4);
@@ -494,6 +496,9 @@ __global__ void k_batch_clear(BatchHeader* hdr, uint32_t* counters, int count, u
     hdr->tail = 0u;
     hdr->done = 0u;
     hdr->error = 0u;
+    hdr->items = 0ull;
+    hdr->wait_ticks = 0ull;
+    hdr->work_ticks = 0ull;
   }
 }
 
@@ -537,8 +542,12 @@ __global__ __launch_bounds__(kBThreads) void k_batch_run(const BatchDesc* descs,
   __shared__ Item sh_item;
   __shared__ BatchDesc sh_desc;
   __shared__ InstLayout sh_layout;
+  // thread 0's running totals: items run, ticks spent claiming and waiting
+  // for a slot, ticks spent running items (added to the header at exit)
+  unsigned long long n_items = 0ull, t_wait = 0ull, t_work = 0ull, t_mark = 0ull;
   for (;;) {
     if (threadIdx.x == 0) {
+      t_mark = wall_clock64();
       const uint32_t h = atomicAdd(&hdr->head, 1u);
       uint32_t ok = 0u;
       if ((int64_t)h < slots) {
@@ -557,9 +566,19 @@ __global__ __launch_bounds__(kBThreads) void k_batch_run(const BatchDesc* descs,
         }
       }
       sh_u[0] = ok;
+      const unsigned long long now = wall_clock64();
+      t_wait += now - t_mark;
+      t_mark = now;
     }
     __syncthreads();
-    if (sh_u[0] == 0u) return;
+    if (sh_u[0] == 0u) {
+      if (threadIdx.x == 0) {
+        atomicAdd(&hdr->items, n_items);
+        atomicAdd(&hdr->wait_ticks, t_wait);
+        atomicAdd(&hdr->work_ticks, t_work);
+      }
+      return;
+    }
     const Item it = sh_item;
     // the instance's descriptor and scratch layout, once per item, in LDS
     // (their arrays are indexed by mode at run time)
@@ -592,6 +611,10 @@ __global__ __launch_bounds__(kBThreads) void k_batch_run(const BatchDesc* descs,
       }
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+      ++n_items;
+      t_work += wall_clock64() - t_mark;
+    }
   }
 }
 
@@ -678,6 +701,14 @@ int32_t hopm_batch_run(const hopm_batch_desc* d_descs, const hopm_batch_plan* pl
   hipLaunchKernelGGL(k_batch_run, dim3(grid), dim3(kBThreads), 0, s, D, plan->count, plan->sweeps, w,
                      items, flags, counters, d_stats, hdr, plan->queue_slots);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(TVC_EHIP, hipGetErrorString(e));
+  return TVC_OK;
+}
+
+int32_t hopm_batch_profile(const void* ws, uint64_t* d_out, void* stream) {
+  if (!ws || !d_out) return fail(TVC_EINVAL, "NULL argument");
+  hipError_t e = hipMemcpyAsync(d_out, &((const BatchHeader*)ws)->items, 3 * sizeof(uint64_t),
+                                hipMemcpyDeviceToDevice, (hipStream_t)stream);
   if (e != hipSuccess) return fail(TVC_EHIP, hipGetErrorString(e));
   return TVC_OK;
 }

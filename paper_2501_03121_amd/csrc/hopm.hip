@@ -142,12 +142,56 @@ __global__ void k_kron(const double* x, KronArgs k, Acc* w, i64 n, const float* 
     i64 rem = r;
     double p = 1.0;
     for (int m = k.nm - 1; m >= 0; --m) {
-      const i64 i = rem % k.dims[m];
-      rem /= k.dims[m];
+      i64 q, i;
+      divmod(rem, k.dims[m], q, i);
+      rem = q;
       p *= x[k.offs[m] + i];
     }
-    if (scale0) p *= (double)scale0[r / sdiv];
+    if (scale0) {
+      i64 q, i;
+      divmod(r, sdiv, q, i);
+      p *= (double)scale0[q];
+    }
     w[r] = (Acc)p;
+  }
+}
+
+// Large weight vectors: the product over the trailing modes whose extents
+// multiply to B <= kKronLo values is formed once per workgroup in LDS, and a
+// workgroup then writes whole chunks of B consecutive weights, each the
+// LDS values times the chunk's product over the leading modes (one index
+// split per chunk instead of one per mode per weight).  Products are formed
+// in FP64 and rounded once.
+constexpr int kKronLo = 4096;
+
+template <typename Acc>
+__global__ __launch_bounds__(256) void k_kron_chunked(const double* x, KronArgs k, int h, i64 B, Acc* w,
+                                                      i64 n) {
+  __shared__ double lo[kKronLo];
+  for (i64 j = threadIdx.x; j < B; j += blockDim.x) {
+    i64 rem = j;
+    double p = 1.0;
+    for (int m = k.nm - 1; m >= k.nm - h; --m) {
+      i64 q, i;
+      divmod(rem, k.dims[m], q, i);
+      rem = q;
+      p *= x[k.offs[m] + i];
+    }
+    lo[j] = p;
+  }
+  __syncthreads();
+  const i64 nchunks = n / B;
+  for (i64 c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    i64 rem = c;
+    double hi = 1.0;
+    for (int m = k.nm - h - 1; m >= 0; --m) {
+      i64 q, i;
+      divmod(rem, k.dims[m], q, i);
+      rem = q;
+      hi *= x[k.offs[m] + i];
+    }
+    Acc* dst = w + c * B;
+    for (i64 j = threadIdx.x; j < B; j += blockDim.x) dst[j] = (Acc)(hi * lo[j]);
   }
 }
 
@@ -316,9 +360,19 @@ tvc_status kron(const Ctx& c, int m0, int m1, Acc* w, const float* scale0, i64 s
     k.offs[m - m0] = Lt.off[m];
     n *= Lt.n[m];
   }
-  const int g = (int)std::max<i64>(1, std::min<i64>((n + 255) / 256, 4 * (i64)device_cus()));
-  hipLaunchKernelGGL((k_kron<Acc>), dim3(g), dim3(256), 0, c.s, (const double*)c.x, k, w, n, scale0,
-                     sdiv);
+  // trailing modes whose product fits the LDS table
+  int h = 0;
+  i64 B = 1;
+  while (h < k.nm && B * k.dims[k.nm - 1 - h] <= kKronLo) B *= k.dims[k.nm - 1 - h++];
+  if (!scale0 && n >= ((i64)1 << 16) && B >= 64) {
+    const int g = (int)std::max<i64>(1, std::min<i64>(n / B, 4 * (i64)device_cus()));
+    hipLaunchKernelGGL((k_kron_chunked<Acc>), dim3(g), dim3(256), 0, c.s, (const double*)c.x, k, h, B,
+                       w, n);
+  } else {
+    const int g = (int)std::max<i64>(1, std::min<i64>((n + 255) / 256, 4 * (i64)device_cus()));
+    hipLaunchKernelGGL((k_kron<Acc>), dim3(g), dim3(256), 0, c.s, (const double*)c.x, k, w, n, scale0,
+                       sdiv);
+  }
   TVC_TRY_HIP(hipGetLastError());
   return TVC_OK;
 }

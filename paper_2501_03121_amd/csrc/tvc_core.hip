@@ -705,10 +705,24 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
     p.family = kRow;
     if (nu > 32) {
       p.lng = true;
-      // rows sharing one weight load: RB rows x 8/RB units per lane keeps 8
-      // loads in flight (units per lane per row: ceil(upr / 64))
+      // RB rows share each weight load and a lane keeps 8/RB units of each
+      // in flight, 8 loads in all.  A row that fits one pass of the wave
+      // (q = ceil(upr / 64) <= 8/RB units per lane) keeps its weights in
+      // registers: take the largest such RB.  Longer rows take RB = 2 (4
+      // contiguous units per row per step stream better than 8 rows of one
+      // unit), except when the weight vector is far larger than the L2
+      // (over 8 MB, the HOPM pass 1 of high orders): then every group of RB
+      // rows re-reads it from beyond the L2, and RB = 8 cuts that traffic 4x.
+      // Measured on gfx950 over the Table 1 and 32^6 sweeps.
       const i64 q = cdiv(p.upr, kWave);
-      p.rb = L >= 8 && q <= 1 ? 8 : (L >= 4 && q <= 3 ? 4 : (L >= 2 ? 2 : 1));
+      int rb = 1;
+      if (q <= 4) {
+        rb = q <= 1 ? 8 : (q <= 2 ? 4 : 2);
+      } else {
+        rb = (M * (i64)acc_bytes(dtype) > ((i64)8 << 20)) ? 8 : 2;
+      }
+      while (rb > 1 && L < rb) rb /= 2;
+      p.rb = rb;
       const i64 groups = cdiv(L, p.rb);
       p.nsplit = 1;
       p.chunk = p.upr;

@@ -117,3 +117,16 @@ def test_batch_planted_recovery(dev):
         got = np.split(host(xs[i]), np.cumsum(specs[i][0])[:-1])
         assert min(abs(float(np.dot(g, v))) for g, v in zip(got, planted[i])) > 0.9
         assert abs(r.lam - lams[i]) < 0.2 * lams[i]
+
+
+def test_batch_profile_counts_every_item(dev):
+    # every queue slot is run exactly once: sweeps * (nt1 + nt2 + 2) per instance
+    As, x0s, _ = make_batch(dev, 10, 4, hi=30)
+    xs = [tvc.pack_vectors(x0, dev) for x0 in x0s]
+    bp = B.prepare(As, xs, 3, tile_elems=512)
+    B.run(bp)
+    torch.cuda.synchronize()
+    assert B.error_word(bp) == 0
+    p = B.profile(bp)
+    assert p["items"] == int(bp.plan.queue_slots)
+    assert p["work_s"] > 0 and p["wait_s"] >= 0 and 0 < p["busy_fraction"] <= 1
