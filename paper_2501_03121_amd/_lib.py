@@ -14,7 +14,7 @@ from pathlib import Path
 import os
 
 # TVC_LIBRARY overrides the library path (e.g. to compare builds).
-LIB_PATH = Path(os.environ.get("TVC_LIBRARY", Path(__file__).resolve().parent / "lib" / "libtvc.so"))
+LIB_PATH = Path(os.environ.get("TVC_LIBRARY") or Path(__file__).resolve().parent / "lib" / "libtvc.so")
 
 TVC_OK, TVC_EINVAL, TVC_EDTYPE, TVC_EALIAS, TVC_EWORKSPACE, TVC_EHIP, TVC_EDEGENERATE, TVC_ENOTCONVERGED = range(8)
 TVC_F64, TVC_F32, TVC_F16, TVC_BF16, TVC_F8E4M3 = range(5)
