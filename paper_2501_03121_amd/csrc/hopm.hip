@@ -195,6 +195,152 @@ __global__ __launch_bounds__(256) void k_kron_chunked(const double* x, KronArgs 
   }
 }
 
+// ---------------------------------------------------------------- small steps
+// The vector side of a sweep, once its operands are small (the n0 x n1
+// matrix, the W chain below 64K values), as a short program that one
+// workgroup runs instead of one launch per step: contract the last or the
+// first mode of a buffer with a vector mirror, normalise into x_j with the
+// sweep's bookkeeping (as k_normalize), and form the pass-2 weights
+// x_0 (x) x_1.  Buffers 0..2 are LDS (kTailElems values each), the others
+// global.
+// Steps are separated by workgroup barriers, so a step sees the vectors the
+// previous normalisations wrote.
+constexpr int kTailThreads = 512;
+constexpr int kTailElems = 2048;
+constexpr int kTailMaxSteps = 24;
+constexpr int kTailLds = 3;
+enum TailOp { kTLast = 0, kTFirst = 1, kTNorm = 2, kTKron = 3 };
+
+struct TailStep {
+  int op, src, dst, mode, flags;
+  i64 a, b;   // kTLast: rows, n; kTFirst: n, rest; kTNorm: n; kTKron: n0, n1
+};
+
+template <typename Acc>
+struct TailProg {
+  int nsteps;
+  TailStep st[kTailMaxSteps];
+  Acc* g[6];                 // global buffers kTailLds ...
+  double* x;
+  Acc* wv;
+  hopm_stats* stats;
+  double* norms;             // optional: ||y|| of step j written to norms[j]
+  const float* scale0;       // kTKron: optional per-row scale (E4M3 slabs)
+  i64 sdiv;
+  i64 off[TVC_MAX_ORDER], woff[TVC_MAX_ORDER];
+};
+
+template <typename Acc>
+__device__ __forceinline__ double tail_block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < kTailThreads / kWave; ++q) t += sh[q];
+  __syncthreads();
+  return t;
+}
+
+template <typename Acc>
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailProg<Acc> p) {
+  __shared__ Acc lds[kTailLds][kTailElems];
+  __shared__ double sh[kTailThreads / kWave];
+  const int tid = threadIdx.x;
+  for (int k = 0; k < p.nsteps; ++k) {
+    const TailStep& q = p.st[k];
+    const Acc* in = nullptr;
+    if (q.src >= 0) in = q.src < kTailLds ? lds[q.src] : p.g[q.src - kTailLds];
+    Acc* out = nullptr;
+    if (q.dst >= 0) out = q.dst < kTailLds ? lds[q.dst] : p.g[q.dst - kTailLds];
+    if (q.op == kTLast) {
+      // out[r] = sum_i in[r * n + i] * w[i]; G lanes per row
+      const i64 rows = q.a, n = q.b;
+      const Acc* w = p.wv + p.woff[q.mode];
+      int G = 1;
+      while (G < kWave && G < n) G <<= 1;
+      const int sub = tid & (G - 1);
+      const int grp = tid / G, ngrp = kTailThreads / G;
+      for (i64 r0 = 0; r0 < rows; r0 += ngrp) {
+        const i64 r = r0 + grp;
+        Acc acc = (Acc)0;
+        if (r < rows)
+          for (i64 i = sub; i < n; i += G) acc = fma(in[r * n + i], w[i], acc);
+        for (int o = G >> 1; o >= 1; o >>= 1) acc += shfl_xor(acc, o);
+        if (sub == 0 && r < rows) out[r] = acc;
+      }
+    } else if (q.op == kTFirst) {
+      // out[c] = sum_i in[i * rest + c] * w[i]
+      const i64 n = q.a, rest = q.b;
+      const Acc* w = p.wv + p.woff[q.mode];
+      for (i64 c = tid; c < rest; c += kTailThreads) {
+        Acc acc = (Acc)0;
+        for (i64 i = 0; i < n; ++i) acc = fma(in[i * rest + c], w[i], acc);
+        out[c] = acc;
+      }
+    } else if (q.op == kTNorm) {
+      const i64 n = q.a;
+      const int j = q.mode;
+      double* x = p.x + p.off[j];
+      Acc* wj = p.wv + p.woff[j];
+      double ss = 0.0;
+      for (i64 i = tid; i < n; i += kTailThreads) {
+        const double v = (double)in[i];
+        ss += v * v;
+      }
+      ss = tail_block_sum<Acc>(ss, sh);
+      const double nrm = sqrt(ss);
+      if (p.norms && tid == 0) p.norms[j] = nrm;
+      if (!(nrm > 0.0) || !isfinite(nrm)) {
+        if (tid == 0) {
+          p.stats->status = TVC_EDEGENERATE;
+          if (q.flags & kFirstJ) p.stats->delta = 0.0;
+          if (q.flags & kLastJ) {
+            p.stats->lambda = nrm;
+            p.stats->sweeps += 1;
+          }
+        }
+      } else {
+        const double inv = 1.0 / nrm;
+        double dd = 0.0;
+        for (i64 i = tid; i < n; i += kTailThreads) {
+          const double v = (double)in[i] * inv;
+          const double df = v - x[i];
+          dd += df * df;
+          x[i] = v;
+          wj[i] = (Acc)v;
+        }
+        dd = tail_block_sum<Acc>(dd, sh);
+        if (tid == 0) {
+          const double dj = sqrt(dd);
+          p.stats->delta = (q.flags & kFirstJ) ? dj : fmax(p.stats->delta, dj);
+          if (q.flags & kLastJ) {
+            p.stats->lambda = nrm;
+            p.stats->sweeps += 1;
+          }
+        }
+      }
+    } else {  // kTKron: out[r] = x_0[r / n1] * x_1[r mod n1] (* scale0[r / sdiv])
+      const i64 n0 = q.a, n1 = q.b;
+      const double* x0 = p.x + p.off[0];
+      const double* x1 = p.x + p.off[1];
+      for (i64 r = tid; r < n0 * n1; r += kTailThreads) {
+        i64 i0, i1;
+        divmod(r, n1, i0, i1);
+        double v = x1[i1] * x0[i0];
+        if (p.scale0) {
+          i64 sq, sr;
+          divmod(r, p.sdiv, sq, sr);
+          v *= (double)p.scale0[sq];
+        }
+        out[r] = (Acc)v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- schedule
 namespace {
 
@@ -383,6 +529,115 @@ tvc_status kron(const Ctx& c, int m0, int m1, Acc* w, const float* scale0, i64 s
     if (s_ != TVC_OK) return s_;      \
   } while (0)
 
+// Inputs in global memory up to this many values are read by the single
+// workgroup of a small-step program (about 32 KB in float32: a few
+// microseconds); larger ones get a full launch.
+constexpr i64 kTailIn = 8192;
+
+// A buffer of a small-step program: LDS slot 0..2 or a global pointer.
+template <typename Acc>
+struct TBufT {
+  int lds_id = -1;
+  Acc* ptr = nullptr;
+  i64 size = 0;
+  static TBufT lds(int id, i64 n) { TBufT b; b.lds_id = id; b.size = n; return b; }
+  static TBufT global(Acc* p, i64 n) { TBufT b; b.ptr = p; b.size = n; return b; }
+  bool is_global() const { return lds_id < 0; }
+};
+
+// An LDS slot holding neither a nor b.
+template <typename B>
+int tl_free_lds(const B& a, const B& b) {
+  for (int i = 0; i < kTailLds; ++i)
+    if (i != a.lds_id && i != b.lds_id) return i;
+  return 0;
+}
+
+// Collects small steps and launches them as one k_tail program.
+template <typename Acc>
+struct Tail {
+  typedef TBufT<Acc> TBuf;
+  const Ctx& c;
+  TailProg<Acc> p{};
+  int nglob = 0;
+
+  explicit Tail(const Ctx& cc) : c(cc) { reset(); }
+
+  void reset() {
+    const Layout& Lt = *c.Lt;
+    p = TailProg<Acc>{};
+    p.x = c.x;
+    p.wv = c.at<Acc>(Lt.o_wv);
+    p.stats = c.st;
+    p.norms = c.norms;
+    p.sdiv = 1;
+    for (int m = 0; m < Lt.d; ++m) {
+      p.off[m] = Lt.off[m];
+      p.woff[m] = Lt.woff[m];
+    }
+    nglob = 0;
+  }
+
+  tvc_status flush() {
+    if (p.nsteps == 0) return TVC_OK;
+    hipLaunchKernelGGL((k_tail<Acc>), dim3(1), dim3(kTailThreads), 0, c.s, p);
+    TVC_TRY_HIP(hipGetLastError());
+    reset();
+    return TVC_OK;
+  }
+
+  // buffer id for the program (registering a global pointer); flushes when
+  // the program is full
+  tvc_status id(const TBuf& b, int* out) {
+    if (!b.is_global()) {
+      *out = b.lds_id;
+      return TVC_OK;
+    }
+    for (int i = 0; i < nglob; ++i)
+      if (p.g[i] == b.ptr) {
+        *out = kTailLds + i;
+        return TVC_OK;
+      }
+    if (nglob == (int)(sizeof(p.g) / sizeof(p.g[0]))) return fail(TVC_EINVAL, "small-step program: too many buffers");
+    p.g[nglob] = b.ptr;
+    *out = kTailLds + nglob++;
+    return TVC_OK;
+  }
+
+  tvc_status add(int op, const TBuf* src, const TBuf* dst, int mode, int flags, i64 a, i64 b) {
+    if (p.nsteps == kTailMaxSteps) return fail(TVC_EINVAL, "small-step program: too many steps");
+    TailStep q{};
+    q.op = op;
+    q.mode = mode;
+    q.flags = flags;
+    q.a = a;
+    q.b = b;
+    q.src = -1;
+    q.dst = -1;
+    if (src) TVC_TRY(id(*src, &q.src));
+    if (dst) TVC_TRY(id(*dst, &q.dst));
+    p.st[p.nsteps++] = q;
+    return TVC_OK;
+  }
+
+  tvc_status last(const TBuf& src, i64 rows, i64 n, int mode, const TBuf& dst) {
+    return add(kTLast, &src, &dst, mode, 0, rows, n);
+  }
+  tvc_status first(const TBuf& src, i64 n, i64 rest, int mode, const TBuf& dst) {
+    return add(kTFirst, &src, &dst, mode, 0, n, rest);
+  }
+  tvc_status norm(const TBuf& src, int j) {
+    const Layout& Lt = *c.Lt;
+    const int flags = (j == 0 ? kFirstJ : 0) | (j == Lt.d - 1 ? kLastJ : 0);
+    return add(kTNorm, &src, nullptr, j, flags, Lt.n[j], 0);
+  }
+  tvc_status kron(const TBuf& dst, i64 n0, i64 n1, const float* scale0, i64 sdiv) {
+    p.scale0 = scale0;
+    p.sdiv = sdiv;
+    return add(kTKron, nullptr, &dst, 0, 0, n0, n1);
+  }
+};
+
 template <typename Acc>
 tvc_status sweep(const Ctx& c) {
   const Layout& Lt = *c.Lt;
@@ -411,6 +666,8 @@ tvc_status sweep(const Ctx& c) {
   Acc* Wb = c.at<Acc>(Lt.o_Wb);
   Acc* Ca = c.at<Acc>(Lt.o_Ca);
   Acc* Cb = c.at<Acc>(Lt.o_Cb);
+  typedef TBufT<Acc> TBuf;
+  Tail<Acc> tl(c);
   // pass 1: M = A contracted over modes 2..d-1
   const Acc* w1 = wv + Lt.woff[2];
   if (d >= 4) {
@@ -419,39 +676,69 @@ tvc_status sweep(const Ctx& c) {
     w1 = w1b;
   }
   TVC_TRY(run(c, A->dtype, A->data, Lt.n01, Lt.R1, 1, w1, Mm, f8 ? A->slab_scale : nullptr, n[1]));
-  // j = 0, 1
-  TVC_TRY(run(c, Lt.acc_dt, Mm, n[0], n[1], 1, wv + Lt.woff[1], y, nullptr, 1));
-  TVC_TRY(normalize<Acc>(c, y, 0));
-  TVC_TRY(run(c, Lt.acc_dt, Mm, 1, n[0], n[1], wv + Lt.woff[0], y, nullptr, 1));
-  TVC_TRY(normalize<Acc>(c, y, 1));
-  // pass 2: W_2 = A contracted with x_0 (x) x_1 (slab scale folded into the weights)
-  TVC_TRY(kron<Acc>(c, 0, 2, w2, f8 ? A->slab_scale : nullptr, n[1]));
-  TVC_TRY(run(c, A->dtype, A->data, 1, Lt.n01, Lt.R1, w2, Wa, nullptr, 1));
-  // j >= 2
-  Acc* Wcur = Wa;
-  Acc* Wother = Wb;
-  i64 wsize = Lt.R1;
-  for (int j = 2; j < d; ++j) {
-    if (j > 2) {
-      TVC_TRY(run(c, Lt.acc_dt, Wcur, 1, n[j - 1], wsize / n[j - 1], wv + Lt.woff[j - 1], Wother,
-                  nullptr, 1));
-      wsize /= n[j - 1];
-      std::swap(Wcur, Wother);
-    }
-    const Acc* src = Wcur;
-    i64 t = wsize;
-    Acc* bufs[2] = {Ca, Cb};
-    int bi = 0;
-    for (int m = d - 1; m > j; --m) {
-      Acc* dst = (m == j + 1) ? y : bufs[bi];
-      TVC_TRY(run(c, Lt.acc_dt, src, t / n[m], n[m], 1, wv + Lt.woff[m], dst, nullptr, 1));
-      t /= n[m];
-      src = dst;
-      bi ^= 1;
-    }
-    TVC_TRY(normalize<Acc>(c, src, j));
+  // j = 0, 1 and the pass-2 weights: one small program when M is small
+  if (Lt.n01 <= kTailIn && n[0] <= kTailElems && n[1] <= kTailElems) {
+    const TBuf m = TBuf::global(Mm, Lt.n01), l0 = TBuf::lds(0, n[0]), l1 = TBuf::lds(1, n[1]);
+    TVC_TRY(tl.last(m, n[0], n[1], 1, l0));
+    TVC_TRY(tl.norm(l0, 0));
+    TVC_TRY(tl.first(m, n[0], n[1], 0, l1));
+    TVC_TRY(tl.norm(l1, 1));
+    TVC_TRY(tl.kron(TBuf::global(w2, Lt.n01), n[0], n[1], f8 ? A->slab_scale : nullptr, n[1]));
+    TVC_TRY(tl.flush());
+  } else {
+    TVC_TRY(run(c, Lt.acc_dt, Mm, n[0], n[1], 1, wv + Lt.woff[1], y, nullptr, 1));
+    TVC_TRY(normalize<Acc>(c, y, 0));
+    TVC_TRY(run(c, Lt.acc_dt, Mm, 1, n[0], n[1], wv + Lt.woff[0], y, nullptr, 1));
+    TVC_TRY(normalize<Acc>(c, y, 1));
+    TVC_TRY(kron<Acc>(c, 0, 2, w2, f8 ? A->slab_scale : nullptr, n[1]));
   }
-  return TVC_OK;
+  // pass 2: W_2 = A contracted with x_0 (x) x_1 (slab scale folded into the weights)
+  TVC_TRY(run(c, A->dtype, A->data, 1, Lt.n01, Lt.R1, w2, Wa, nullptr, 1));
+  // j >= 2.  A step whose input is in global memory and larger than kTailIn
+  // values is a full launch (after the pending program, whose vectors it
+  // may need); smaller steps join the program, with outputs in LDS when
+  // they fit.
+  TBuf W = TBuf::global(Wa, Lt.R1);
+  Acc* wfree = Wb;   // the global W buffer not holding W
+  for (int j = 2; j < d; ++j) {
+    if (j > 2) {   // W_j = W_{j-1} contracted over its first mode (j - 1)
+      const i64 out = W.size / n[j - 1];
+      if (W.is_global() && W.size > kTailIn) {
+        TVC_TRY(tl.flush());
+        TVC_TRY(run(c, Lt.acc_dt, W.ptr, 1, n[j - 1], out, wv + Lt.woff[j - 1], wfree, nullptr, 1));
+        Acc* old = W.ptr;
+        W = TBuf::global(wfree, out);
+        wfree = old;
+      } else {
+        TBuf dst = out <= kTailElems ? TBuf::lds(tl_free_lds(W, W), out)
+                                     : TBuf::global(W.is_global() && W.ptr == Wa ? Wb : Wa, out);
+        TVC_TRY(tl.first(W, n[j - 1], out, j - 1, dst));
+        if (dst.is_global()) wfree = (dst.ptr == Wa) ? Wb : Wa;
+        W = dst;
+      }
+    }
+    // y_j = W_j contracted over modes d-1 .. j+1
+    TBuf src = W;
+    i64 t = W.size;
+    for (int m = d - 1; m > j; --m) {
+      const i64 out = t / n[m];
+      TBuf dst;
+      if (src.is_global() && t > kTailIn) {
+        TVC_TRY(tl.flush());
+        Acc* o = (m == j + 1) ? y : ((src.ptr == Ca) ? Cb : Ca);
+        TVC_TRY(run(c, Lt.acc_dt, src.ptr, out, n[m], 1, wv + Lt.woff[m], o, nullptr, 1));
+        dst = TBuf::global(o, out);
+      } else {
+        dst = out <= kTailElems ? TBuf::lds(tl_free_lds(W, src), out)
+                                : TBuf::global((src.is_global() && src.ptr == Ca) ? Cb : Ca, out);
+        TVC_TRY(tl.last(src, out, n[m], m, dst));
+      }
+      src = dst;
+      t = out;
+    }
+    TVC_TRY(tl.norm(src, j));
+  }
+  return tl.flush();
 }
 
 template <typename Acc>
