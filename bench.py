@@ -91,7 +91,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the contraction shards without communication, see DESIGN.md)", file=sys.stderr)
+              "(the contraction shards along a non-contracted mode without communication; only one device is measured here)", file=sys.stderr)
         return 2
 
     import numpy as np
