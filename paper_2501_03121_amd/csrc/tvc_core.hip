@@ -192,6 +192,14 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
     for (int r = 0; r < RB; ++r)
 #pragma unroll
       for (int e = 0; e < NA; ++e) acc[r][e] = (Acc)0;
+    // Ragged row end (vector path): lane r < RB loads the last EU elements
+    // of row r now, so that the load overlaps the stream below instead of
+    // adding a round trip after it; the EU - tail elements the last full
+    // unit covered are skipped when it is added.
+    const bool tail_task = a.tail > 0 && s == a.nsplit - 1;
+    const bool tail_lane = tail_task && lane < RB && row0 + lane < a.L;
+    typename U::Raw traw = U::zero();
+    if (tail_lane) traw = U::load(a.A, (row0 + lane) * a.ld + a.ld - EU);
     for (i64 u = u0 + lane; u < u1; u += (i64)kWave * KU) {
       typename U::Raw raw[KU][RB];
 #pragma unroll
@@ -223,23 +231,18 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
           for (int e = 0; e < EU; ++e) acc[r][e % NA] = fma(v[e], wv[k][e], acc[r][e % NA]);
         }
     }
-    // Ragged row end (vector path): lane 0 reads the last EU elements of the
-    // row and skips the EU - tail of them that the last full unit covered.
-    if (a.tail > 0 && s == a.nsplit - 1 && lane == 0) {
+    if (tail_lane) {
       const int from = EU - a.tail;
-      Acc wt[EU];
+      Acc wt[EU], v[EU];
       load_w<Acc, EU>(wr, a.ld - EU, wt);
+      U::unpack(traw, v);
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const i64 row = row0 + r;
-        if (row < a.L) {
-          Acc v[EU];
-          U::unpack(U::load(a.A, row * a.ld + a.ld - EU), v);
+      for (int r = 0; r < RB; ++r)
+        if (r == lane) {
 #pragma unroll
           for (int e = 0; e < EU; ++e)
             if (e >= from) acc[r][e % NA] = fma(v[e], wt[e], acc[r][e % NA]);
         }
-      }
     }
     // Cross-lane reduction of the RB row sums as a butterfly: each of the
     // first log2(RB) exchanges hands half of a lane's rows to its partner,
@@ -670,16 +673,17 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
   p.upr = p.vec ? len / epv : len;
   p.tail = p.vec ? (int)(len % epv) : 0;
   const i64 nu = p.upr + (p.tail > 0 ? 1 : 0);
-  // Small slabs: stage whole slabs through LDS where the row and slab
-  // kernels lose coalescing (measured on gfx950 over the Table 1 shapes):
-  // rows of 33-64 units (a wave per row, too short to stream), and slabs of
-  // at most 4 KB whose right extent is ragged, not a power of two, or at
-  // most 2 units wide.  Short rows (<= 32 units) and power-of-two slab
-  // widths stay with their own kernels, which are faster there.  A block of
-  // sb slabs must be a multiple of 16 bytes.
+  // Small slabs: stage whole slabs through LDS where the slab kernel loses
+  // coalescing (measured on gfx950 over the Table 1 shapes): slabs of at
+  // most 4 KB whose right extent is ragged, not a power of two, or at most
+  // 2 units wide.  Power-of-two slab widths stay with the slab kernel,
+  // which is faster there.  Rows (R == 1) of 33-64 units are staged only in
+  // float64, where the row kernel's double accumulators limit occupancy;
+  // in the other formats the row kernel is 10-40% faster on them.  A block
+  // of sb slabs must be a multiple of 16 bytes.
   const i64 sbytes = M * R * b;
   const bool pow2 = (nu & (nu - 1)) == 0;
-  const bool small = R == 1 ? (p.vec && nu > 32 && nu <= 64)
+  const bool small = R == 1 ? (dtype == TVC_F64 && p.vec && nu > 32 && nu <= 64)
                             : (sbytes <= 4096 && nu <= 32 && (p.tail > 0 || !pow2 || nu <= 2));
   if (a16 && small && !tuning().stage_off) {
     const i64 q = 16 / gcd_(16, sbytes);

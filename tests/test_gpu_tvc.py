@@ -164,10 +164,10 @@ def test_ragged_vector_rows(dev, fmt, no_stage):
 # very narrow right extent.  The cases cover a single partial block, a ragged
 # last block, one-element right extents and several blocks per workgroup.
 def _staged_cases(fmt):
-    rl = 45 * EPV[fmt] + {"f64": 1, "f32": 1, "f16": 2, "bf16": 2, "e4m3": 4}[fmt]
-    return [((3000, rl), 1), ((7, 11, rl), 2), ((13,) * 5, 3), ((50, 37, 13), 1),
-            ((1001, 3, 7), 1), ((9, 15, 31), 1), ((3, 5, 7), 1), ((6, 7, 1, 9), 2),
-            ((2, 3, 4, 5, 6, 7), 4)]
+    # rows of 33-64 units are staged only in float64
+    rows = [((3000, 91), 1), ((7, 11, 91), 2)] if fmt == "f64" else []
+    return rows + [((13,) * 5, 3), ((50, 37, 13), 1), ((1001, 3, 7), 1), ((9, 15, 31), 1),
+                   ((3, 5, 7), 1), ((6, 7, 1, 9), 2), ((2, 3, 4, 5, 6, 7), 4)]
 
 
 @pytest.mark.parametrize("fmt", FMTS)
