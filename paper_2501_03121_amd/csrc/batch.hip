@@ -251,6 +251,15 @@ __device__ bool wg_tile_done(uint32_t* counter, int ntiles, uint32_t* sh_flag) {
   return *sh_flag != 0;
 }
 
+// A pointer every lane holds the same value of (read from LDS), moved to
+// scalar registers.
+__device__ __forceinline__ const char* uniform_ptr(const void* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (const char*)(((uint64_t)hi << 32) | lo);
+}
+
 // ---------------------------------------------------------------- phases
 // Rows [r0, r1) of a float matrix with R columns: 16-byte loads at dword
 // alignment (row starts are 4-byte aligned), the ragged end of a row read as
@@ -283,6 +292,8 @@ __device__ void phase_p1(const BatchDesc& D, const InstLayout& L, float* s, int 
   const int lane = lane_id();
   const int sub = lane & (G - 1), rsub = lane >> g;
   const int wave = threadIdx.x / kWave;
+  // the tile is far below 2^31 bytes: lanes address it with 32-bit offsets
+  const char* tbase = uniform_ptr(D.A + r0 * R);
   for (int64_t rb = r0 + (int64_t)wave * P * RU; rb < r1; rb += (int64_t)NW * P * RU) {
     float acc[RU];
 #pragma unroll
@@ -297,7 +308,7 @@ __device__ void phase_p1(const BatchDesc& D, const InstLayout& L, float* s, int 
 #pragma unroll
       for (int j = 0; j < RU; ++j) {
         const int64_t row = rb + (int64_t)j * P + rsub;
-        raw[j] = row < r1 ? stream_load16(D.A + row * R + e) : uint4{0u, 0u, 0u, 0u};
+        raw[j] = row < r1 ? stream_load16(tbase + (uint32_t)(((row - r0) * R + e) * 4)) : uint4{0u, 0u, 0u, 0u};
       }
 #pragma unroll
       for (int j = 0; j < RU; ++j) {
@@ -343,6 +354,7 @@ __device__ void phase_p2(const BatchDesc& D, const InstLayout& L, float* s, int 
   while (((int64_t)1 << g) < nu && g < 8) ++g;
   const int TC = 1 << g, RG = kBThreads >> g;
   const int tc = threadIdx.x & (TC - 1), rg = threadIdx.x >> g;
+  const char* tbase = uniform_ptr(D.A + r0 * R);   // 32-bit lane offsets below
   for (int64_t cb = 0; cb < nu; cb += TC) {
     const int64_t u = cb + tc;
     const bool on = u < nu;
@@ -356,7 +368,7 @@ __device__ void phase_p2(const BatchDesc& D, const InstLayout& L, float* s, int 
       for (int k = 0; k < UN; ++k) {
         const int64_t rk = row + (int64_t)k * RG;
         const bool ok = rk < r1;
-        raw[k] = (on && ok) ? stream_load16(D.A + rk * R + e) : uint4{0u, 0u, 0u, 0u};
+        raw[k] = (on && ok) ? stream_load16(tbase + (uint32_t)(((rk - r0) * R + e) * 4)) : uint4{0u, 0u, 0u, 0u};
         wr[k] = ok ? w2[rk] : 0.f;
       }
 #pragma unroll

@@ -74,3 +74,28 @@ def test_full_size_bf16_lambda_error(dev):
     x = tvc.pack_vectors(x0, dev)
     r32 = tvc.hopm_solve(A, x, tol=1e-6, max_sweeps=200)
     assert abs(r32.lam - ref.lam) <= 1e-5 * ref.lam
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("dims", [(65537, 65537), (3, 65537, 21847)], ids=["65537^2", "3x65537x21847"])
+def test_over_2e32_elements(dev, dims):
+    # More than 2^32 elements (17.2 GB in float32) in every mode: 64-bit
+    # element offsets, rows of more than 2^31 bytes cut into chunks, and the
+    # 64-bit branch of the task index split.  Sampled outputs against the
+    # oracle on the gathered fibers A[l, :, r].
+    assert int(np.prod(dims)) > 2 ** 32
+    A = synth.device_normal(dims, 120, dev)
+    for k in range(len(dims)):
+        xh = synth.unit_vectors([dims[k]], 320 + k)[0].astype(np.float32)
+        y = tvc.contract(A, torch.from_numpy(xh).to(dev), k)
+        u, n, v = O.matricized_dims(dims, k)
+        g = synth.rng(11 + k)
+        li = torch.from_numpy(g.integers(0, u, 64)).to(dev)
+        ri = torch.from_numpy(g.integers(0, v, 64)).to(dev)
+        fibers = host(A.view(u, n, v)[li, :, ri])            # (64, n), exact device values
+        ref = O.tvc(fibers.reshape(64, n, 1), xh, 1).reshape(-1)
+        got = host(y.view(u, v)[li, ri])
+        assert O.rel_err(got, ref) < 1e-5, (dims, k)
+        del y
+    del A
+    torch.cuda.empty_cache()
