@@ -526,6 +526,7 @@ def run_batch(dev, count: int = 512, sweeps: int = 50):
            "pct_peak": round(100 * nbytes / t / 1e9 / PEAK_HBM_GBS, 1), "tile_elems": te, "grid": grid,
            "error_word": err, "degenerate": sum(r.status != 0 for r in res),
            "work_items": prof["items"], "grid_busy_fraction": round(prof["busy_fraction"], 3),
+           "grid_seconds_per_phase": {k: round(v, 4) for k, v in prof["phase_s"].items()},
            "autotune": table}
     log(json.dumps({k: v for k, v in out.items() if k != "autotune"}))
     return out

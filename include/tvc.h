@@ -295,13 +295,14 @@ int32_t hopm_batch_run(const hopm_batch_desc* d_descs, const hopm_batch_plan* pl
                        void* stream);
 int32_t hopm_batch_error(const void* ws, uint32_t* d_error_out, void* stream);
 
-/* Profile of the last hopm_batch_run on this workspace: copies three
- * uint64 values to device memory d_out (asynchronously on `stream`): work
- * items run, and wall-clock ticks (100 MHz) summed over workgroups spent
- * (1) claiming a queue slot and waiting for it to be published and (2)
- * running items.  Their ratio shows how much of the persistent grid idles
- * on the dependencies between phases.  Returns TVC_OK, TVC_EINVAL for NULL
- * pointers or TVC_EHIP. */
+/* Profile of the last hopm_batch_run on this workspace: copies six uint64
+ * values to device memory d_out (asynchronously on `stream`): work items
+ * run; wall-clock ticks (100 MHz) summed over workgroups spent claiming a
+ * queue slot and waiting for it to be published; and ticks spent running
+ * items of each of the four phases (pass-1 tiles, the x_0/x_1 step, pass-2
+ * tiles, the W chain).  The waiting share shows how much of the persistent
+ * grid idles on the dependencies between phases.  Returns TVC_OK,
+ * TVC_EINVAL for NULL pointers or TVC_EHIP. */
 int32_t hopm_batch_profile(const void* ws, uint64_t* d_out, void* stream);
 
 /* ---------------------------------------------------------------------------

@@ -99,11 +99,14 @@ def profile(bp: BatchPlan) -> dict:
     """Work items run and the persistent grid's time split (seconds summed
     over workgroups) between waiting for queue slots and running items, for
     the last run on this plan's workspace."""
-    out = torch.zeros(3, dtype=torch.int64, device=bp.ws.device)
+    out = torch.zeros(6, dtype=torch.int64, device=bp.ws.device)
     s = torch.cuda.current_stream().cuda_stream
     L.check(L.lib().hopm_batch_profile(_ws_ptr(bp), out.data_ptr(), s))
-    items, wait, work = (int(v) for v in out.cpu().tolist())
+    items, wait, p1, s1, p2, s2 = (int(v) for v in out.cpu().tolist())
+    work = p1 + s1 + p2 + s2
     return {"items": items, "wait_s": wait / 1e8, "work_s": work / 1e8,
+            "phase_s": {"pass1_tiles": p1 / 1e8, "x0_x1": s1 / 1e8, "pass2_tiles": p2 / 1e8,
+                        "w_chain": s2 / 1e8},
             "busy_fraction": work / max(wait + work, 1)}
 
 

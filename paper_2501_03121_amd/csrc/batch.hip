@@ -55,8 +55,9 @@ struct BatchHeader {
   uint32_t tail;
   uint32_t done;
   uint32_t error;
-  // profile of the last run (wall clock ticks summed over workgroups)
-  unsigned long long items, wait_ticks, work_ticks;
+  // profile of the last run (wall clock ticks summed over workgroups):
+  // items run, ticks waiting for slots, ticks running items of each phase
+  unsigned long long items, wait_ticks, work_ticks[4];
 };
 
 constexpr int kBThreads = 256;
@@ -510,7 +511,7 @@ __global__ void k_batch_clear(BatchHeader* hdr, uint32_t* counters, int count, u
     hdr->error = 0u;
     hdr->items = 0ull;
     hdr->wait_ticks = 0ull;
-    hdr->work_ticks = 0ull;
+    for (int q = 0; q < 4; ++q) hdr->work_ticks[q] = 0ull;
   }
 }
 
@@ -556,7 +557,8 @@ __global__ __launch_bounds__(kBThreads) void k_batch_run(const BatchDesc* descs,
   __shared__ InstLayout sh_layout;
   // thread 0's running totals: items run, ticks spent claiming and waiting
   // for a slot, ticks spent running items (added to the header at exit)
-  unsigned long long n_items = 0ull, t_wait = 0ull, t_work = 0ull, t_mark = 0ull;
+  unsigned long long n_items = 0ull, t_wait = 0ull, t_mark = 0ull;
+  unsigned long long t_work[4] = {0ull, 0ull, 0ull, 0ull};
   for (;;) {
     if (threadIdx.x == 0) {
       t_mark = wall_clock64();
@@ -587,7 +589,7 @@ __global__ __launch_bounds__(kBThreads) void k_batch_run(const BatchDesc* descs,
       if (threadIdx.x == 0) {
         atomicAdd(&hdr->items, n_items);
         atomicAdd(&hdr->wait_ticks, t_wait);
-        atomicAdd(&hdr->work_ticks, t_work);
+        for (int q = 0; q < 4; ++q) atomicAdd(&hdr->work_ticks[q], t_work[q]);
       }
       return;
     }
@@ -625,7 +627,10 @@ __global__ __launch_bounds__(kBThreads) void k_batch_run(const BatchDesc* descs,
     __syncthreads();
     if (threadIdx.x == 0) {
       ++n_items;
-      t_work += wall_clock64() - t_mark;
+      const unsigned long long dt = wall_clock64() - t_mark;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q == it.phase) t_work[q] += dt;
     }
   }
 }
@@ -719,7 +724,7 @@ int32_t hopm_batch_run(const hopm_batch_desc* d_descs, const hopm_batch_plan* pl
 
 int32_t hopm_batch_profile(const void* ws, uint64_t* d_out, void* stream) {
   if (!ws || !d_out) return fail(TVC_EINVAL, "NULL argument");
-  hipError_t e = hipMemcpyAsync(d_out, &((const BatchHeader*)ws)->items, 3 * sizeof(uint64_t),
+  hipError_t e = hipMemcpyAsync(d_out, &((const BatchHeader*)ws)->items, 6 * sizeof(uint64_t),
                                 hipMemcpyDeviceToDevice, (hipStream_t)stream);
   if (e != hipSuccess) return fail(TVC_EHIP, hipGetErrorString(e));
   return TVC_OK;

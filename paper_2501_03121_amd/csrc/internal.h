@@ -36,13 +36,13 @@ struct TvcPlan {
   int grid = 1;          // workgroups launched
   size_t part_bytes = 0; // partial-sum scratch (nsplit > 1)
   i64 sb = 0;            // kStage: slabs per LDS block
+  int stage_vb = 0;      // kStage: 16 = 16-byte LDS reads, 0 = one element per read
 };
 
 struct Tuning {
   int blocks_per_cu[4] = {0, 0, 0, 0};
   bool stage_off = false;  // never pick the LDS-staged family
   int split_m = 0;
-  int unroll = 0;
 };
 Tuning& tuning();
 

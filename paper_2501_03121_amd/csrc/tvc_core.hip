@@ -478,7 +478,12 @@ __global__ __launch_bounds__(kBlock) void k_slab(ColArgs<typename St<DT>::Acc> a
 // into LDS with 16-byte loads, each thread holding kStageVecs/256 of them,
 // issues the loads of its next block, and computes the current block's
 // sb*R outputs from LDS while those loads are in flight.  G = 2^glog lanes
-// per output split the contracted extent and combine with shuffles.
+// per output group split the contracted extent and combine with shuffles.
+// For 4- and 8-byte elements, when a slab row is a whole number of 16-byte
+// words, an output group is the VE = 16 / element-size consecutive columns
+// one LDS word holds, so each LDS read feeds VE accumulators (measured:
+// narrow formats lose more to the wider groups' reductions and LDS bank
+// conflicts than they gain, so they read one element at a time).
 constexpr int kStageBytes = 32768;
 constexpr int kStageVecs = kStageBytes / 16;
 constexpr int kStagePer = kStageVecs / kBlock;
@@ -492,11 +497,12 @@ struct StageArgs {
   const float* oscale; i64 odiv;
 };
 
-template <int DT, int ROLE>
+template <int DT, int ROLE, int VB>
 __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<typename St<DT>::Acc> a) {
   typedef typename St<DT>::Acc Acc;
   typedef typename St<DT>::T T;
   constexpr int EB = (int)sizeof(T);
+  constexpr int VE = VB == 0 ? 1 : VB / EB;   // columns per output group
   __shared__ uint4 lds[kStageVecs];
   const int tid = threadIdx.x;
   const i64 E = a.M * a.R;
@@ -533,26 +539,44 @@ __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<typename St<DT>::Acc
     }
     __syncthreads();
     if (b + gridDim.x < a.nblocks) issue(b + gridDim.x);
-    const i64 nout = ns * a.R;
+    const i64 Rv = a.R / VE;          // output groups per slab row
+    const i64 nout = ns * Rv;
     const T* sl = (const T*)lds;
-    for (i64 o = tid >> a.glog; o < a.sb * a.R; o += kBlock >> a.glog) {
-      Acc acc0 = (Acc)0, acc1 = (Acc)0;
-      i64 ls, rr;
-      divmod(o, a.R, ls, rr);
+    for (i64 o = tid >> a.glog; o < a.sb * Rv; o += kBlock >> a.glog) {
+      Acc acc0[VE], acc1[VE];
+#pragma unroll
+      for (int v = 0; v < VE; ++v) acc0[v] = acc1[v] = (Acc)0;
+      i64 ls, rv;
+      divmod(o, Rv, ls, rv);
       if (o < nout) {
-        const i64 base = ls * E + rr;
+        const i64 base = ls * E + rv * VE;
+        auto step = [&](i64 m, Acc* acc) {
+          const i64 e = base + m * a.R;
+          Acc val[VE];
+          if constexpr (VB == 16) {
+            unpack16<DT>(*(const uint4*)(sl + e), val);
+          } else {
+            val[0] = load_elem<DT>(sl, e);
+          }
+          const Acc wm = a.w[m];
+#pragma unroll
+          for (int v = 0; v < VE; ++v) acc[v] = fma(val[v], wm, acc[v]);
+        };
         i64 m = sub;
         for (; m + G < a.M; m += 2 * G) {
-          acc0 = fma(load_elem<DT>(sl, base + m * a.R), a.w[m], acc0);
-          acc1 = fma(load_elem<DT>(sl, base + (m + G) * a.R), a.w[m + G], acc1);
+          step(m, acc0);
+          step(m + G, acc1);
         }
-        if (m < a.M) acc0 = fma(load_elem<DT>(sl, base + m * a.R), a.w[m], acc0);
+        if (m < a.M) step(m, acc0);
       }
-      Acc v = acc0 + acc1;
-      for (int off = G >> 1; off >= 1; off >>= 1) v += shfl_xor(v, off);
-      if (sub == 0 && o < nout) {
-        const i64 idx = l0 * a.R + o;
-        a.y[idx] = epilogue(v, a.y, idx, l0 + ls, a.alpha, a.beta, a.oscale, a.odiv);
+#pragma unroll
+      for (int v = 0; v < VE; ++v) {
+        Acc t = acc0[v] + acc1[v];
+        for (int off = G >> 1; off >= 1; off >>= 1) t += shfl_xor(t, off);
+        if (sub == 0 && o < nout) {
+          const i64 idx = l0 * a.R + o * VE + v;
+          a.y[idx] = epilogue(t, a.y, idx, l0 + ls, a.alpha, a.beta, a.oscale, a.odiv);
+        }
       }
     }
   }
@@ -692,9 +716,13 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
       p.family = kStage;
       p.sb = sb;
       p.vec = true;
-      // lanes per output: as many as keep all 256 threads busy (measured:
-      // a whole wave per row serialises the row reductions and is slower)
-      const i64 outs = std::max<i64>(sb * R, 1);
+      // LDS word per read: 16 bytes for 4- and 8-byte elements when a slab
+      // row is a whole number of them, else one element
+      p.stage_vb = (b >= 4 && (R * b) % 16 == 0) ? 16 : 0;
+      const i64 ve = p.stage_vb == 0 ? 1 : p.stage_vb / b;
+      // lanes per output group: as many as keep all 256 threads busy
+      // (measured: a whole wave per row serialises the reductions)
+      const i64 outs = std::max<i64>(sb * R / ve, 1);
       int g = 0;
       while (g < 6 && ((i64)2 << g) * outs <= kBlock && ((i64)1 << g) < M) ++g;
       p.glog = g;
@@ -812,7 +840,9 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
   const dim3 grd(p.grid);
   if (p.family == kStage) {
     StageArgs<Acc> a{A, w, y, L, M, R, p.sb, p.tasks, p.glog, (Acc)alpha, (Acc)beta, oscale, odiv};
-    hipLaunchKernelGGL((k_stage<DT, ROLE>), grd, blk, 0, st, a);
+    if (p.stage_vb == 16 && (DT == TVC_F32 || DT == TVC_F64))
+      hipLaunchKernelGGL((k_stage<DT, ROLE, (DT == TVC_F32 || DT == TVC_F64) ? 16 : 0>), grd, blk, 0, st, a);
+    else hipLaunchKernelGGL((k_stage<DT, ROLE, 0>), grd, blk, 0, st, a);
     return hipGetLastError();
   }
   if (p.family == kRow) {

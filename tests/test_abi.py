@@ -104,3 +104,34 @@ def test_workspace_sizes_are_aligned_and_monotone():
     assert small % 256 == 0 and big % 256 == 0 and big > small
     assert lib.tvc_contract_workspace_bytes(tensor((1 << 20,)), 0) > 0   # long single row splits
     assert lib.tvc_contract_workspace_bytes(tensor((64, 64, 64)), 1) == 0
+
+
+def test_batch_and_tuning_argument_errors():
+    lib = L.lib()
+    assert lib.hopm_batch_profile(None, 1 << 20, None) == L.TVC_EINVAL
+    assert lib.hopm_batch_profile(1 << 20, None, None) == L.TVC_EINVAL
+    assert lib.hopm_batch_error(None, 1 << 20, None) == L.TVC_EINVAL
+    assert lib.hopm_batch_error(1 << 20, None, None) == L.TVC_EINVAL
+    plan = L.HopmBatchPlan()
+    descs = (L.HopmBatchDesc * 1)()
+    d = descs[0]
+    d.A, d.x, d.order = 1 << 20, 1 << 22, 2
+    d.dims[0] = d.dims[1] = 8
+    assert lib.hopm_batch_prepare(descs, 1, 5, 0, ctypes.byref(plan)) == L.TVC_EINVAL   # order < 3
+    d.order, d.dims[2] = 3, 8
+    assert lib.hopm_batch_prepare(descs, 0, 5, 0, ctypes.byref(plan)) == L.TVC_EINVAL   # no instances
+    assert lib.hopm_batch_prepare(descs, 1, 0, 0, ctypes.byref(plan)) == L.TVC_EINVAL   # no sweeps
+    assert lib.hopm_batch_prepare(descs, 1, 5, 0, ctypes.byref(plan)) == L.TVC_OK
+    assert plan.queue_slots == 5 * (descs[0].nt1 + descs[0].nt2 + 2)
+    assert lib.hopm_batch_run(None, ctypes.byref(plan), 0, 1 << 24, plan.ws_bytes, 1 << 22, None) == L.TVC_EINVAL
+    assert lib.hopm_batch_run(1 << 20, ctypes.byref(plan), 0, 1 << 24, plan.ws_bytes - 1, 1 << 22, None) == L.TVC_EWORKSPACE
+    assert lib.tvc_set_tuning(4, 0, 0) == L.TVC_EINVAL
+    assert lib.tvc_set_tuning(1, 0, 3) == L.TVC_EINVAL
+    t = tensor((64, 9, 12), dtype=L.TVC_F32)             # small slabs: staged family
+    info = (ctypes.c_int32 * 8)()
+    assert lib.tvc_contract_plan(t, 1, info, 8) == L.TVC_OK and info[0] == 3
+    assert lib.tvc_set_tuning(3, -1, 0) == L.TVC_OK      # staged family off ...
+    assert lib.tvc_contract_plan(t, 1, info, 8) == L.TVC_OK and info[0] == 2
+    assert lib.tvc_set_tuning(3, 0, 0) == L.TVC_OK       # ... and on again
+    assert lib.tvc_contract_plan(t, 1, info, 8) == L.TVC_OK and info[0] == 3
+    assert lib.tvc_contract_plan(t, 1, None, 8) == L.TVC_EINVAL

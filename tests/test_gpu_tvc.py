@@ -166,8 +166,11 @@ def test_ragged_vector_rows(dev, fmt, no_stage):
 def _staged_cases(fmt):
     # rows of 33-64 units are staged only in float64
     rows = [((3000, 91), 1), ((7, 11, 91), 2)] if fmt == "f64" else []
-    return rows + [((13,) * 5, 3), ((50, 37, 13), 1), ((1001, 3, 7), 1), ((9, 15, 31), 1),
-                   ((3, 5, 7), 1), ((6, 7, 1, 9), 2), ((2, 3, 4, 5, 6, 7), 4)]
+    # right extents 12 and 20 are whole 16-byte words in float32 and float64:
+    # the staged kernel then reads several columns per LDS word
+    words = [((64, 9, 12), 1), ((300, 5, 20), 1)] + ([((500, 6, 32), 1)] if fmt == "e4m3" else [])
+    return rows + words + [((13,) * 5, 3), ((50, 37, 13), 1), ((1001, 3, 7), 1), ((9, 15, 31), 1),
+                           ((3, 5, 7), 1), ((6, 7, 1, 9), 2), ((2, 3, 4, 5, 6, 7), 4)]
 
 
 @pytest.mark.parametrize("fmt", FMTS)
