@@ -51,7 +51,7 @@ def measured_traffic():
     FETCH_SIZE / WRITE_SIZE counter runs, or None if the kernel source has
     changed since those counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "tvc_col_f32_traffic.json")
+    path = os.path.join(ROOT, "profiles", "tvc_colw_f32_32p6_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -203,10 +203,11 @@ def main() -> int:
                        "pct_peak": round(100 * b / (med * 1e-3) / 1e9 / PEAK_HBM_GBS, 1)}
     log(json.dumps(per_op))
 
-    # dominant kernel: the column-streaming contraction kernel (float32,
-    # 16-byte loads, 4 wave groups) launched by tvc_contract
+    # dominant kernel: the short-column contraction kernel with the LDS
+    # output window (float32, 16-byte loads, 4 waves per workgroup) that
+    # tvc_contract launches for the 32^6 modes 0-3
     dom = [(lbl, b) for (lbl, _, b, p) in tvc_calls
-           if p["family"] == "col" and p["vec"] and p["split_m"] == 4 and p["nsplit"] == 1]
+           if p["family"] == "col" and p["vec"] and p["window"] and p["nsplit"] == 1]
     dom_ms, dom_b = [], []
     for lbl, b in dom:
         j = [o[0] for o in ops].index(lbl)
@@ -217,7 +218,7 @@ def main() -> int:
     achieved = avg_b / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "tvc::k_col<1, true, 4, 0> (float32 column streaming)",
+                "kernel": "tvc::k_colw<1, true, 0, 4> (float32 short columns, LDS output window)",
                 "launches_per_step": len(dom), "avg_launch_ms": round(avg_ms, 4),
                 "avg_bytes_per_launch": int(avg_b)}
 

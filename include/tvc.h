@@ -127,7 +127,10 @@ int32_t tvc_contract(const tvc_tensor* A, int32_t mode, const void* x, void* y,
  * workgroups launched, [5] lanes per row (families 0 and 2, 0 = a wave per
  * row; family 3: lanes per output), [6] elements of each contiguous row after its last whole 16-byte
  * vector (vector path only; such rows need only start on a 4-byte
- * boundary), [7] full 16-byte vectors (or elements, scalar path) per row.
+ * boundary), [7] full 16-byte vectors (or elements, scalar path) per row,
+ * [8] 1 if each workgroup collects its outputs in an LDS window and writes
+ * them in bursts (short contracted extents, where y is a sizeable share of
+ * the traffic).
  * Returns TVC_OK or an argument error. */
 int32_t tvc_contract_plan(const tvc_tensor* A, int32_t mode, int32_t* info, int32_t n);
 
@@ -312,8 +315,9 @@ int32_t hopm_batch_profile(const void* ws, uint64_t* d_out, void* stream);
  * blocks_per_cu caps the persistent grid at that many 256-thread workgroups
  * per compute unit; for family 3 a negative value turns the family off (the
  * dispatcher then uses families 0 and 2 for those shapes).  split_m (family
- * 1 only: 1, 2 or 4) is the number of wave groups sharing one column tile.
- * Values of 0 restore the built-in choice.  Process-wide; set it while no
+ * 1 only: 1, 2 or 4) is the number of wave groups sharing one column tile;
+ * a negative split_m turns the LDS output window off (outputs are stored
+ * as each tile finishes).  Values of 0 restore the built-in choice.  Process-wide; set it while no
  * other thread is launching contractions.
  * ------------------------------------------------------------------------- */
 int32_t tvc_set_tuning(int32_t family, int32_t blocks_per_cu, int32_t split_m);

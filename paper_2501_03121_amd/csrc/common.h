@@ -184,6 +184,39 @@ __device__ __forceinline__ Acc wave_sum(Acc v) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// A lane permutation within each row of 16 lanes (a DPP operand modifier:
+// no LDS traffic, a few cycles).  CTRL: 0xB1 swaps neighbouring lanes,
+// 0x4E swaps neighbouring pairs, 0x141 mirrors each half-row of 8 lanes,
+// 0x140 mirrors the row.
+template <int CTRL>
+__device__ __forceinline__ float dpp_perm(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm(double v) {
+  const uint64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Sum over aligned groups of 2^glog lanes (glog <= 6); every lane of a group
+// gets its group's sum, added in the same order in every group.  Within a
+// row of 16 lanes the partners come from DPP permutations (after the first
+// two steps each group of 4 holds its sum, which the half-row mirror pairs
+// with the neighbouring group of 4, and the row mirror pairs halves); 32-
+// and 64-lane groups finish with two cross-row shuffles.
+template <typename Acc>
+__device__ __forceinline__ Acc group_sum(Acc v, int glog) {
+  if (glog >= 1) v += dpp_perm<0xB1>(v);
+  if (glog >= 2) v += dpp_perm<0x4E>(v);
+  if (glog >= 3) v += dpp_perm<0x141>(v);
+  if (glog >= 4) v += dpp_perm<0x140>(v);
+  if (glog >= 5) v += shfl_xor(v, 16);
+  if (glog >= 6) v += shfl_xor(v, 32);
+  return v;
+}
+
 // q = a / b, r = a mod b for non-negative a, b > 0: 32-bit division when
 // both fit (task and row indices almost always do), 64-bit otherwise.
 __device__ __forceinline__ void divmod(i64 a, i64 b, i64& q, i64& r) {

@@ -37,11 +37,14 @@ struct TvcPlan {
   size_t part_bytes = 0; // partial-sum scratch (nsplit > 1)
   i64 sb = 0;            // kStage: slabs per LDS block
   int stage_vb = 0;      // kStage: 16 = 16-byte LDS reads, 0 = one element per read
+  bool win = false;      // outputs written through an LDS window in bursts
+  int wv = 4;            // waves per workgroup of the windowed column and slab kernels
 };
 
 struct Tuning {
   int blocks_per_cu[4] = {0, 0, 0, 0};
   bool stage_off = false;  // never pick the LDS-staged family
+  bool win_off = false;    // never write outputs through an LDS window
   int split_m = 0;
 };
 Tuning& tuning();

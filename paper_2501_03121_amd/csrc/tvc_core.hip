@@ -48,6 +48,26 @@ constexpr int kUnroll = TVC_UNROLL;             // per row: long rows, column gr
 constexpr int kShortUnroll = TVC_SHORT_UNROLL;  // short rows
 constexpr int kSlabUnroll = TVC_SLAB_UNROLL;    // slabs
 constexpr int kCol1Unroll = TVC_COL1_UNROLL;    // column streaming with one wave group
+// Short columns and slabs with the output window: WV waves per workgroup,
+// each keeping 32 / WV loads in flight.  Measured on gfx950: 4 waves of 8
+// loads for 32 or more rows, 8 waves of 4 loads for fewer (the per-strip
+// work is then short, and more waves hide its latency).
+template <int WV>
+struct ColwShape {
+  static constexpr int kThreads = WV * kWave;
+  static constexpr int kUnroll = 32 / WV;
+};
+constexpr int kColwMaxThreads = 8 * kWave;
+// Short rows with the window: a row-group reduction per row, so more waves
+// per workgroup (1024 threads) to hide its latency, 8 rows per lane per task.
+#ifndef TVC_ROWSW_UNROLL
+#define TVC_ROWSW_UNROLL 8
+#endif
+#ifndef TVC_ROWSW_WAVES
+#define TVC_ROWSW_WAVES 16
+#endif
+constexpr int kRowswUnroll = TVC_ROWSW_UNROLL;       // rows per lane per task
+constexpr int kRowswThreads = TVC_ROWSW_WAVES * 64;  // threads per workgroup
 
 template <typename Acc>
 struct RowArgs {
@@ -100,6 +120,72 @@ __device__ __forceinline__ TaskRange wave_tasks(i64 ntasks) {
 
 __device__ __forceinline__ TaskRange block_tasks(i64 ntasks) {
   return TaskRange{(i64)blockIdx.x, ntasks, (i64)gridDim.x};
+}
+
+// A contiguous range of tasks per workgroup.
+__device__ __forceinline__ TaskRange block_range(i64 ntasks) {
+  const i64 per = (ntasks + gridDim.x - 1) / gridDim.x;
+  const i64 b = (i64)blockIdx.x * per;
+  return TaskRange{b, min(ntasks, b + per), 1};
+}
+
+// ------------------------------------------------------------ output window
+// Small writes spread through a read stream cost HBM far more than their
+// bytes (measured on gfx950 with 32-row columns, where y is 1/32 of A: the
+// 1 KB stores of each task cut the read rate by a fifth, while the same
+// outputs written in 64-128 KB bursts per workgroup cost about their bytes).
+// A workgroup that produces one contiguous stretch of y in increasing order
+// therefore parks finished outputs in LDS and writes them in bursts: the
+// window holds y[base, base + kWinElems) and is flushed when the next task's
+// outputs would not fit, and at the end.
+#ifndef TVC_WIN_BYTES
+#define TVC_WIN_BYTES 131072
+#endif
+constexpr int kWinBytes = TVC_WIN_BYTES;
+// longest contracted extent given a window (its weights are kept in LDS)
+#ifndef TVC_WIN_MAXM
+#define TVC_WIN_MAXM 256
+#endif
+constexpr int kWinMaxM = TVC_WIN_MAXM;
+// a window holds at least one round's outputs (up to 16 waves of 64 lanes,
+// each lane with 16 float outputs (columns) or 8 rows of 1 output)
+static_assert(kWinBytes == 0 || kWinBytes >= 65536, "window below a round's outputs");
+
+template <typename Acc>
+struct Win {
+  static constexpr int kElems = kWinBytes > 0 ? kWinBytes / (int)sizeof(Acc) : 1;
+};
+
+// Window slot 0 is y[org], the last 16-byte boundary at or before y[base],
+// so whole 16-byte groups of slots land on whole 16-byte groups of y.
+template <typename Acc>
+__device__ __forceinline__ i64 win_origin(const Acc* y, i64 base) {
+  return base - (i64)(((uintptr_t)(y + base) & 15) / sizeof(Acc));
+}
+
+// Writes y[base, end) from the window whose slot 0 is y[org]: 16-byte
+// stores for the whole groups, element stores for the partial groups at
+// either end.  Called by the whole workgroup.
+template <typename Acc, int NT = kBlock>
+__device__ __forceinline__ void win_flush(Acc* y, const Acc* win, i64 org, i64 base, i64 end) {
+  constexpr int V = 16 / (int)sizeof(Acc);
+  __syncthreads();
+  const int lo = (int)(base - org), hi = (int)(end - org);
+  const int g0 = (lo + V - 1) / V, g1 = hi / V;
+  Acc* dst = y + org;
+  if (g0 >= g1) {
+    for (int i = lo + threadIdx.x; i < hi; i += NT) dst[i] = win[i];
+  } else {
+    const int head = g0 * V - lo, tail = hi - g1 * V;
+    if ((int)threadIdx.x < head) dst[lo + threadIdx.x] = win[lo + threadIdx.x];
+    if ((int)threadIdx.x >= NT - tail) {
+      const int i = g1 * V + (threadIdx.x - (NT - tail));
+      dst[i] = win[i];
+    }
+    for (int g = g0 + threadIdx.x; g < g1; g += NT)
+      __builtin_nontemporal_store(*(const u32x4*)(win + g * V), (u32x4*)(dst + g * V));
+  }
+  __syncthreads();
 }
 
 // EU consecutive values to dst; a ragged last unit stores only its elements
@@ -329,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void k_row_short(RowArgs<typename St<DT>::A
       Acc s_ = (Acc)0;
 #pragma unroll
       for (int e = 0; e < EU; ++e) s_ = fma(v[e], wv[e], s_);
-      for (int off = G >> 1; off >= 1; off >>= 1) s_ += shfl_xor(s_, off);
+      s_ = group_sum(s_, a.glog);
       const i64 row = base + (i64)k * P + rsub;
       if (sub == 0 && row < a.L)
         a.y[row] = epilogue(s_, a.y, row, row, a.alpha, a.beta, a.oscale, a.odiv);
@@ -410,6 +496,101 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a)
   }
 }
 
+// ------------------------------------------------------ kCol, short columns
+// Short contracted extents, outputs through the LDS window: a wave owns a
+// strip of 64 column units of one slab and streams all M rows of it, UN
+// loads in flight (no combine across waves, so no barrier per task).  The
+// strips of a workgroup's contiguous range go to its four waves in rounds;
+// a round's outputs are one stretch of y, and the window is flushed between
+// rounds when the next round's stretch would not fit.  The M weights are
+// copied to LDS once, so the row loop issues no vector loads but A's.
+template <int DT, bool VEC, int ROLE, int WV>
+__global__ __launch_bounds__(ColwShape<WV>::kThreads) void k_colw(ColArgs<typename St<DT>::Acc> a) {
+  typedef typename St<DT>::Acc Acc;
+  typedef Unit<DT, VEC> U;
+  constexpr int EU = U::EU;
+  constexpr int NT = ColwShape<WV>::kThreads;
+  constexpr int UN = ColwShape<WV>::kUnroll;
+  constexpr int WPB = WV;
+  constexpr i64 SW = (i64)kWave * EU;  // elements of y per strip
+  __shared__ __align__(16) Acc win[Win<Acc>::kElems];
+  __shared__ Acc wl[kWinMaxM];
+  const int lane = lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int M = (int)a.M;
+  for (int i = threadIdx.x; i < M; i += NT) wl[i] = a.w[i];
+  __syncthreads();
+  const TaskRange tr = block_range(a.L * a.ctiles);
+  i64 org = 0, wbase = 0, wend = 0;
+  for (i64 t0 = tr.begin; t0 < tr.end; t0 += WPB) {
+    const i64 tlast = min(t0 + WPB, tr.end) - 1;
+    i64 l0, c0, l1, c1;
+    divmod(t0, a.ctiles, l0, c0);
+    divmod(tlast, a.ctiles, l1, c1);
+    const i64 ys = l0 * a.R + c0 * SW;
+    const i64 ye = l1 * a.R + min(a.R, (c1 + 1) * SW);
+    if (t0 == tr.begin) {
+      wbase = ys;
+      org = win_origin(a.y, ys);
+    } else if (ye - org > Win<Acc>::kElems) {
+      win_flush<Acc, NT>(a.y, win, org, wbase, ys);
+      wbase = ys;
+      org = win_origin(a.y, ys);
+    }
+    wend = ye;
+    const i64 t = t0 + wv;
+    if (t > tlast) continue;
+    i64 l, ct;
+    divmod(t, a.ctiles, l, ct);
+    const i64 c = ct * kWave + lane;
+    const bool tl = a.tail > 0 && c == a.upr;
+    if (!(c < a.upr || tl)) continue;
+    const i64 eo = tl ? a.R - EU : c * EU;
+    const char* base = (const char*)a.A + (l * a.M * a.R + eo) * (i64)sizeof(typename St<DT>::T);
+    const i64 rs = a.R * (i64)sizeof(typename St<DT>::T);  // row stride, bytes
+    Acc acc[EU];
+#pragma unroll
+    for (int e = 0; e < EU; ++e) acc[e] = (Acc)0;
+    int m = 0;
+    for (; m + UN <= M; m += UN) {
+      typename U::Raw raw[UN];
+#pragma unroll
+      for (int k = 0; k < UN; ++k) raw[k] = U::load(base + (i64)(m + k) * rs, 0);
+#pragma unroll
+      for (int k = 0; k < UN; ++k) {
+        Acc v[EU];
+        U::unpack(raw[k], v);
+        const Acc wk = wl[m + k];
+#pragma unroll
+        for (int e = 0; e < EU; ++e) acc[e] = fma(v[e], wk, acc[e]);
+      }
+    }
+    if (m < M) {
+      // the last M mod UN rows, loads issued together (M is uniform)
+      typename U::Raw raw[UN - 1];
+#pragma unroll
+      for (int k = 0; k < UN - 1; ++k) raw[k] = m + k < M ? U::load(base + (i64)(m + k) * rs, 0) : U::zero();
+#pragma unroll
+      for (int k = 0; k < UN - 1; ++k) {
+        if (m + k < M) {
+          Acc v[EU];
+          U::unpack(raw[k], v);
+          const Acc wk = wl[m + k];
+#pragma unroll
+          for (int e = 0; e < EU; ++e) acc[e] = fma(v[e], wk, acc[e]);
+        }
+      }
+    }
+    const i64 idx = l * a.R + eo;
+    const int from = tl ? EU - a.tail : 0;
+    Acc* wp = win + (idx - org);
+#pragma unroll
+    for (int e = 0; e < EU; ++e)
+      if (e >= from) wp[e] = epilogue(acc[e], a.y, idx + e, l, a.alpha, a.beta, a.oscale, a.odiv);
+  }
+  if (tr.begin < tr.end) win_flush<Acc, NT>(a.y, win, org, wbase, wend);
+}
+
 // ---------------------------------------------------------------- kSlab
 // Small right extent (R <= 32 units).  A wave covers P = 64/G consecutive
 // slabs: lane (q, c) = (lane / G, lane mod G) owns column unit c of slab
@@ -469,6 +650,167 @@ __global__ __launch_bounds__(kBlock) void k_slab(ColArgs<typename St<DT>::Acc> a
       else store_epilogue<Acc, EU>(acc, a.y, idx, l, a.alpha, a.beta, a.oscale, a.odiv, from);
     }
   }
+}
+
+// ------------------------------------------------- kSlab / kRow, windowed
+// The slab and short-row kernels with the LDS output window, for short
+// contracted extents (the slab kernel) and short rows: a workgroup takes a
+// contiguous range of wave tasks in rounds of one task per wave, whose
+// outputs are one stretch of y; it is flushed as in k_colw.
+
+// Slabs: the lane layout of k_slab; the M weights are staged in LDS and the
+// row loop is unmasked.
+template <int DT, bool VEC, int ROLE, int WV>
+__global__ __launch_bounds__(ColwShape<WV>::kThreads) void k_slabw(ColArgs<typename St<DT>::Acc> a) {
+  typedef typename St<DT>::Acc Acc;
+  typedef typename St<DT>::T T;
+  typedef Unit<DT, VEC> U;
+  constexpr int EU = U::EU;
+  constexpr int NT = ColwShape<WV>::kThreads;
+  constexpr int UN = ColwShape<WV>::kUnroll;
+  constexpr int WPB = WV;
+  __shared__ __align__(16) Acc win[Win<Acc>::kElems];
+  __shared__ Acc wl[kWinMaxM];
+  const int lane = lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int G = 1 << a.glog;
+  const int P = kWave >> a.glog;
+  const int q = lane >> a.glog;
+  const int c = lane & (G - 1);
+  const int M = (int)a.M;
+  for (int i = threadIdx.x; i < M; i += NT) wl[i] = a.w[i];
+  __syncthreads();
+  const bool tl = a.tail > 0 && c == a.upr;
+  const bool cu = c < a.upr || tl;
+  const i64 eo = tl ? a.R - EU : (i64)c * EU;
+  const int from = tl ? EU - a.tail : 0;
+  const i64 rs = a.R * (i64)sizeof(T);
+  const TaskRange tr = block_range((a.L + P - 1) / P);
+  i64 org = 0, wbase = 0, wend = 0;
+  for (i64 t0 = tr.begin; t0 < tr.end; t0 += WPB) {
+    const i64 tlast = min(t0 + WPB, tr.end) - 1;
+    const i64 ys = t0 * P * a.R;
+    const i64 ye = min(a.L, (tlast + 1) * P) * a.R;
+    if (t0 == tr.begin) {
+      wbase = ys;
+      org = win_origin(a.y, ys);
+    } else if (ye - org > Win<Acc>::kElems) {
+      win_flush<Acc, NT>(a.y, win, org, wbase, ys);
+      wbase = ys;
+      org = win_origin(a.y, ys);
+    }
+    wend = ye;
+    const i64 g = t0 + wv;
+    const i64 l = g * P + q;
+    if (g > tlast || !cu || l >= a.L) continue;
+    const char* base = (const char*)a.A + (l * a.M * a.R + eo) * (i64)sizeof(T);
+    Acc acc[EU];
+#pragma unroll
+    for (int e = 0; e < EU; ++e) acc[e] = (Acc)0;
+    int m = 0;
+    for (; m + UN <= M; m += UN) {
+      typename U::Raw raw[UN];
+#pragma unroll
+      for (int k = 0; k < UN; ++k) raw[k] = U::load(base + (i64)(m + k) * rs, 0);
+#pragma unroll
+      for (int k = 0; k < UN; ++k) {
+        Acc v[EU];
+        U::unpack(raw[k], v);
+        const Acc wk = wl[m + k];
+#pragma unroll
+        for (int e = 0; e < EU; ++e) acc[e] = fma(v[e], wk, acc[e]);
+      }
+    }
+    if (m < M) {
+      // the last M mod UN rows, loads issued together (M is uniform)
+      typename U::Raw raw[UN - 1];
+#pragma unroll
+      for (int k = 0; k < UN - 1; ++k) raw[k] = m + k < M ? U::load(base + (i64)(m + k) * rs, 0) : U::zero();
+#pragma unroll
+      for (int k = 0; k < UN - 1; ++k) {
+        if (m + k < M) {
+          Acc v[EU];
+          U::unpack(raw[k], v);
+          const Acc wk = wl[m + k];
+#pragma unroll
+          for (int e = 0; e < EU; ++e) acc[e] = fma(v[e], wk, acc[e]);
+        }
+      }
+    }
+    const i64 idx = l * a.R + eo;
+    Acc* wp = win + (idx - org);
+#pragma unroll
+    for (int e = 0; e < EU; ++e)
+      if (e >= from) wp[e] = epilogue(acc[e], a.y, idx + e, l, a.alpha, a.beta, a.oscale, a.odiv);
+  }
+  if (tr.begin < tr.end) win_flush<Acc, NT>(a.y, win, org, wbase, wend);
+}
+
+// Short rows: the lane layout of k_row_short with UN rows per lane per task.
+template <int DT, bool VEC, int ROLE>
+__global__ __launch_bounds__(kRowswThreads) void k_rowsw(RowArgs<typename St<DT>::Acc> a) {
+  typedef typename St<DT>::Acc Acc;
+  typedef Unit<DT, VEC> U;
+  constexpr int EU = U::EU;
+  constexpr int UN = kRowswUnroll;
+  constexpr int WPB = kRowswThreads / kWave;
+  __shared__ __align__(16) Acc win[Win<Acc>::kElems];
+  const int lane = lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int G = 1 << a.glog;
+  const int P = kWave >> a.glog;
+  const int sub = lane & (G - 1);
+  const int rsub = lane >> a.glog;
+  const bool tl = a.tail > 0 && sub == a.upr;
+  const bool active = sub < a.upr || tl;
+  const i64 eo = tl ? a.ld - EU : (i64)sub * EU;
+  const int from = tl ? EU - a.tail : 0;
+  Acc wk[EU];
+  if (active) {
+    load_w<Acc, EU>(a.w, eo, wk);
+  } else {
+#pragma unroll
+    for (int e = 0; e < EU; ++e) wk[e] = (Acc)0;
+  }
+  const i64 per = (i64)P * UN;
+  const TaskRange tr = block_range((a.L + per - 1) / per);
+  i64 org = 0, wbase = 0, wend = 0;
+  for (i64 t0 = tr.begin; t0 < tr.end; t0 += WPB) {
+    const i64 tlast = min(t0 + WPB, tr.end) - 1;
+    const i64 ys = t0 * per;
+    const i64 ye = min(a.L, (tlast + 1) * per);
+    if (t0 == tr.begin) {
+      wbase = ys;
+      org = win_origin(a.y, ys);
+    } else if (ye - org > Win<Acc>::kElems) {
+      win_flush<Acc, kRowswThreads>(a.y, win, org, wbase, ys);
+      wbase = ys;
+      org = win_origin(a.y, ys);
+    }
+    wend = ye;
+    const i64 t = t0 + wv;
+    if (t > tlast) continue;
+    const i64 base = t * per;
+    typename U::Raw raw[UN];
+#pragma unroll
+    for (int k = 0; k < UN; ++k) {
+      const i64 row = base + (i64)k * P + rsub;
+      raw[k] = (active && row < a.L) ? U::load(a.A, row * a.ld + eo) : U::zero();
+    }
+#pragma unroll
+    for (int k = 0; k < UN; ++k) {
+      Acc v[EU];
+      U::unpack(raw[k], v);
+      Acc s_ = (Acc)0;
+#pragma unroll
+      for (int e = 0; e < EU; ++e) s_ = fma(e < from ? (Acc)0 : v[e], wk[e], s_);
+      s_ = group_sum(s_, a.glog);
+      const i64 row = base + (i64)k * P + rsub;
+      if (sub == 0 && row < a.L)
+        win[row - org] = epilogue(s_, a.y, row, row, a.alpha, a.beta, a.oscale, a.odiv);
+    }
+  }
+  if (tr.begin < tr.end) win_flush<Acc, kRowswThreads>(a.y, win, org, wbase, wend);
 }
 
 // ---------------------------------------------------------------- kStage
@@ -662,6 +1004,18 @@ int ceil_log2(i64 v) {
 
 i64 cdiv(i64 a, i64 b) { return (a + b - 1) / b; }
 
+#ifndef TVC_WIN_BPC
+#define TVC_WIN_BPC 1
+#endif
+constexpr bool kWinOn = kWinBytes > 0;
+constexpr int kWinBlocksPerCu = TVC_WIN_BPC;    // workgroups per CU with a window
+
+// The output window pays where y is a sizeable share of the traffic (short
+// contracted extents) and every workgroup gets several rounds of wave tasks.
+bool win_ok(i64 M, i64 wave_tasks) {
+  return kWinOn && !tuning().win_off && M <= kWinMaxM && wave_tasks >= 16 * (i64)device_cus();
+}
+
 int grid_for(i64 blocks_needed, int family, int default_bpc) {
   int bpc = tuning().blocks_per_cu[family] > 0 ? tuning().blocks_per_cu[family] : default_bpc;
   i64 cap = (i64)bpc * device_cus();
@@ -783,6 +1137,12 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
       const i64 per = (i64)(kWave >> p.glog) * kShortUnroll;
       p.tasks = cdiv(L, per);
       p.grid = grid_for(cdiv(p.tasks, waves_per_block), kRow, 4);
+      const i64 wtasks = cdiv(L, (i64)(kWave >> p.glog) * kRowswUnroll);
+      if (win_ok(M, wtasks)) {
+        p.win = true;
+        p.tasks = wtasks;
+        p.grid = grid_for(cdiv(p.tasks, kRowswThreads / kWave), kRow, kWinBlocksPerCu);
+      }
     }
   } else {
     if (nu > 32) {
@@ -804,6 +1164,17 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
       }
       p.tasks = tasks * p.nsplit;
       p.grid = grid_for(p.tasks, kCol, 4);
+      // Short columns (no split of M): a wave per 64-unit strip, outputs
+      // through the LDS window, as many workgroups per CU as windows fit.
+      if (p.nsplit == 1 && win_ok(M, L * cdiv(nu, kWave))) {
+        p.win = true;
+        p.wv = M < 32 ? 8 : 4;
+        p.tasks = L * cdiv(nu, kWave);
+        p.grid = grid_for(cdiv(p.tasks, p.wv), kCol, kWinBlocksPerCu);
+#ifdef TVC_WIN_GRID_SUB
+        p.grid = std::max(1, p.grid - TVC_WIN_GRID_SUB);
+#endif
+      }
     } else {
       p.family = kSlab;
       p.glog = ceil_log2(std::max<i64>(nu, 1));
@@ -820,6 +1191,11 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
       }
       p.tasks = groups * p.nsplit;
       p.grid = grid_for(cdiv(p.tasks, waves_per_block), kSlab, 4);
+      if (p.nsplit == 1 && win_ok(M, groups)) {
+        p.win = true;
+        p.wv = M < 32 ? 8 : 4;
+        p.grid = grid_for(cdiv(p.tasks, p.wv), kSlab, kWinBlocksPerCu);
+      }
     }
   }
   p.part_bytes = p.nsplit > 1 ? align256((size_t)p.nsplit * (size_t)(L * R) * ab) : 0;
@@ -860,17 +1236,31 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
         else if (p.rb == 2) hipLaunchKernelGGL((k_row_long<DT, false, 2, ROLE>), grd, blk, 0, st, a);
         else hipLaunchKernelGGL((k_row_long<DT, false, 1, ROLE>), grd, blk, 0, st, a);
       }
+    } else if (p.win) {
+      const dim3 wblk(kRowswThreads);
+      if (p.vec) hipLaunchKernelGGL((k_rowsw<DT, true, ROLE>), grd, wblk, 0, st, a);
+      else hipLaunchKernelGGL((k_rowsw<DT, false, ROLE>), grd, wblk, 0, st, a);
     } else {
       if (p.vec) hipLaunchKernelGGL((k_row_short<DT, true, ROLE>), grd, blk, 0, st, a);
       else hipLaunchKernelGGL((k_row_short<DT, false, ROLE>), grd, blk, 0, st, a);
     }
   } else {
-    const i64 tc = kBlock / p.splitm;
+    const i64 tc = (p.family == kCol && p.win) ? kWave : kBlock / p.splitm;
     const i64 nu = p.upr + (p.tail > 0 ? 1 : 0);
     ColArgs<Acc> a{A, w, y, part, L, M, p.upr, R, (nu + tc - 1) / tc, p.chunk, p.nsplit,
                    p.glog, (Acc)alpha, (Acc)beta, oscale, odiv, p.tail};
     if (p.family == kCol) {
-      if (p.vec) {
+      if (p.win) {
+        if (p.wv == 8) {
+          const dim3 wblk(ColwShape<8>::kThreads);
+          if (p.vec) hipLaunchKernelGGL((k_colw<DT, true, ROLE, 8>), grd, wblk, 0, st, a);
+          else hipLaunchKernelGGL((k_colw<DT, false, ROLE, 8>), grd, wblk, 0, st, a);
+        } else {
+          const dim3 wblk(ColwShape<4>::kThreads);
+          if (p.vec) hipLaunchKernelGGL((k_colw<DT, true, ROLE, 4>), grd, wblk, 0, st, a);
+          else hipLaunchKernelGGL((k_colw<DT, false, ROLE, 4>), grd, wblk, 0, st, a);
+        }
+      } else if (p.vec) {
         if (p.splitm == 4) hipLaunchKernelGGL((k_col<DT, true, 4, ROLE>), grd, blk, 0, st, a);
         else if (p.splitm == 2) hipLaunchKernelGGL((k_col<DT, true, 2, ROLE>), grd, blk, 0, st, a);
         else hipLaunchKernelGGL((k_col<DT, true, 1, ROLE>), grd, blk, 0, st, a);
@@ -878,6 +1268,16 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
         if (p.splitm == 4) hipLaunchKernelGGL((k_col<DT, false, 4, ROLE>), grd, blk, 0, st, a);
         else if (p.splitm == 2) hipLaunchKernelGGL((k_col<DT, false, 2, ROLE>), grd, blk, 0, st, a);
         else hipLaunchKernelGGL((k_col<DT, false, 1, ROLE>), grd, blk, 0, st, a);
+      }
+    } else if (p.win) {
+      if (p.wv == 8) {
+        const dim3 wblk(ColwShape<8>::kThreads);
+        if (p.vec) hipLaunchKernelGGL((k_slabw<DT, true, ROLE, 8>), grd, wblk, 0, st, a);
+        else hipLaunchKernelGGL((k_slabw<DT, false, ROLE, 8>), grd, wblk, 0, st, a);
+      } else {
+        const dim3 wblk(ColwShape<4>::kThreads);
+        if (p.vec) hipLaunchKernelGGL((k_slabw<DT, true, ROLE, 4>), grd, wblk, 0, st, a);
+        else hipLaunchKernelGGL((k_slabw<DT, false, ROLE, 4>), grd, wblk, 0, st, a);
       }
     } else {
       if (p.vec) hipLaunchKernelGGL((k_slab<DT, true, ROLE>), grd, blk, 0, st, a);
@@ -933,6 +1333,12 @@ hipError_t run_rows_pw_dt(const void* A, i64 L, i64 M, const void* w_, i64 wdiv,
 
 TvcPlan plan_rows_pw(int dtype, i64 L, i64 M, bool a4, bool w4, i64 wdiv) {
   TvcPlan p = plan_tvc(dtype, L, M, 1, a4, w4, false);
+  if (p.win) {
+    // row-dependent weights: the plain short-row kernel
+    p.win = false;
+    p.tasks = cdiv(L, (i64)(kWave >> p.glog) * kShortUnroll);
+    p.grid = grid_for(cdiv(p.tasks, kBlock / kWave), kRow, 4);
+  }
   if (p.lng) {
     // RB rows of a wave share one weight row: RB must divide wdiv (row
     // groups start at multiples of RB)

@@ -135,3 +135,12 @@ def test_batch_and_tuning_argument_errors():
     assert lib.tvc_set_tuning(3, 0, 0) == L.TVC_OK       # ... and on again
     assert lib.tvc_contract_plan(t, 1, info, 8) == L.TVC_OK and info[0] == 3
     assert lib.tvc_contract_plan(t, 1, None, 8) == L.TVC_EINVAL
+    t = tensor((32,) * 6, dtype=L.TVC_F32)               # short columns: output window
+    info = (ctypes.c_int32 * 9)()
+    assert lib.tvc_contract_plan(t, 2, info, 9) == L.TVC_OK and info[0] == 1 and info[8] == 1
+    assert lib.tvc_set_tuning(1, 0, -1) == L.TVC_OK      # window off ...
+    assert lib.tvc_contract_plan(t, 2, info, 9) == L.TVC_OK and info[8] == 0
+    assert lib.tvc_set_tuning(1, 0, 0) == L.TVC_OK       # ... and on again
+    assert lib.tvc_contract_plan(t, 2, info, 9) == L.TVC_OK and info[8] == 1
+    t = tensor((64, 1024, 1024), dtype=L.TVC_F32)        # long columns: direct stores
+    assert lib.tvc_contract_plan(t, 1, info, 9) == L.TVC_OK and info[0] == 1 and info[8] == 0

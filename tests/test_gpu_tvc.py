@@ -218,3 +218,99 @@ def test_weights_at_4_byte_offset(dev):
     x = big[1:]          # 4-byte aligned, not 16
     y = tvc.contract(A, x, 1)
     assert O.rel_err(host(y), O.tvc(exact, xh.astype(np.float32), 1)) < 1e-5
+
+
+# Short columns write y through an LDS window in bursts, a wave per strip of
+# columns summing all M rows (for problems with enough strips to give every
+# workgroup several rounds).  (8, 3 * 2^22 + e/2) makes every workgroup
+# flush its window mid-range and ends rows raggedly; the others have a
+# ragged 3-d middle mode and one-strip slabs, with a beta term.  On integer
+# inputs (exact sums) the window kernel and the column kernel agree bit for
+# bit.
+def _window_cases(fmt):
+    e = EPV[fmt]
+    return [((8, (3 << 22) + e // 2), 0), ((64, 12, 20001), 1), ((4096, 12, 40 * e + e // 2), 1)]
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_output_window(dev, fmt):
+    for i, (dims, k) in enumerate(_window_cases(fmt)):
+        A, S, exact = stored_tensor(dims, fmt, 23, dev)
+        p = tvc.contract_plan(A, k, scale=S)
+        assert p["family"] == "col" and p["window"] and p["nsplit"] == 1, (fmt, dims, k, p)
+        x, xh = vec(dims[k], 24 + k, fmt, dev)
+        if i == 0:
+            # (8, n) in mode 0: sampled outputs against the oracle's
+            # definition, one by one
+            ah = host(tvc.contract(A, x, k, scale=S))
+            xs = xh.astype(np.float64)
+            js = np.concatenate([synth.integers(60, 26, 0, dims[1] - 1).astype(np.int64),
+                                 np.arange(dims[1] - 4, dims[1])])
+            for j in js:
+                want = float(np.dot(exact[:, j], xs))
+                bound = TOL[fmt] * float(np.abs(exact[:, j]) @ np.abs(xs))
+                assert abs(float(ah[j]) - want) <= bound, (fmt, j)
+            continue
+        y0 = synth.uniform(O.output_dims(dims, k), 25 + k)
+        out = torch.from_numpy(y0).to(torch.float64 if fmt == "f64" else torch.float32).to(dev)
+        tvc.contract(A, x, k, alpha=0.5, beta=-1.25, out=out, scale=S)
+        ref = O.tvc(exact, xh, k, alpha=0.5, beta=-1.25, y=y0)
+        assert O.rel_err(host(out), ref) <= TOL[fmt], (fmt, dims, k)
+
+
+def test_output_window_equals_column_kernel_on_integers(dev):
+    from paper_2501_03121_amd import tune
+    for dims, k in _window_cases("f32"):
+        base = synth.integers(dims, 27, -8, 8)
+        A = torch.from_numpy(base).float().to(dev)
+        xh = synth.integers(dims[k], 28, -4, 4)
+        x = torch.from_numpy(xh).float().to(dev)
+        assert tvc.contract_plan(A, k)["window"]
+        a = tvc.contract(A, x, k).clone()
+        tune.set_tuning("col", 0, -1)
+        try:
+            assert not tvc.contract_plan(A, k)["window"]
+            b = tvc.contract(A, x, k)
+        finally:
+            tune.reset()
+        assert torch.equal(a, b), (dims, k)
+        if np.prod(dims) <= 1 << 25:
+            assert np.array_equal(host(a), O.tvc(base, xh, k)), (dims, k)
+
+
+# The slab and short-row kernels with the output window: many short rows,
+# and many slabs of a power-of-two right extent (the slab family; ragged or
+# other small slabs go to the LDS-staged family unless it is off).  They sum
+# in the same order as the kernels without the window, so the two agree bit
+# for bit on any input.
+SLAB_R = {"f64": 16, "f32": 32, "f16": 64, "bf16": 64, "e4m3": 128}
+
+
+def _windowed_cases(fmt):
+    lg, sh, _ = RAGGED_LEN[fmt]
+    return [((1200000, sh), 1, "row", False), ((70000, 9, SLAB_R[fmt]), 1, "slab", False),
+            ((150000, 9, sh), 1, "slab", True), ((20000, 7, 8, sh), 3, "row", False)]
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_windowed_rows_and_slabs(dev, fmt):
+    from paper_2501_03121_amd import tune
+    for dims, k, family, nostage in _windowed_cases(fmt):
+        A, S, exact = stored_tensor(dims, fmt, 29, dev)
+        if nostage:
+            tune.set_tuning("stage", -1)
+        try:
+            p = tvc.contract_plan(A, k, scale=S)
+            assert p["family"] == family and p["window"], (fmt, dims, k, p)
+            x, xh = vec(dims[k], 30 + k, fmt, dev)
+            y0 = synth.uniform(O.output_dims(dims, k), 31 + k)
+            out = torch.from_numpy(y0).to(torch.float64 if fmt == "f64" else torch.float32).to(dev)
+            a = tvc.contract(A, x, k, alpha=0.5, beta=-1.25, out=out.clone(), scale=S)
+            tune.set_tuning("col", 0, -1)
+            assert not tvc.contract_plan(A, k, scale=S)["window"]
+            b = tvc.contract(A, x, k, alpha=0.5, beta=-1.25, out=out.clone(), scale=S)
+        finally:
+            tune.reset()
+        assert torch.equal(a, b), (fmt, dims, k)
+        ref = O.tvc(exact, xh, k, alpha=0.5, beta=-1.25, y=y0)
+        assert O.rel_err(host(a), ref) <= TOL[fmt], (fmt, dims, k)
