@@ -203,11 +203,11 @@ def main() -> int:
                        "pct_peak": round(100 * b / (med * 1e-3) / 1e9 / PEAK_HBM_GBS, 1)}
     log(json.dumps(per_op))
 
-    # dominant kernel: the short-column contraction kernel with the LDS
-    # output window (float32, 16-byte loads, 4 waves per workgroup) that
-    # tvc_contract launches for the 32^6 modes 0-3
+    # dominant kernel: the column-strip contraction kernel with the LDS
+    # output window (float32, 16-byte loads, 4 waves per workgroup, 4 column
+    # units per lane) that tvc_contract launches for the 32^6 modes 0-2
     dom = [(lbl, b) for (lbl, _, b, p) in tvc_calls
-           if p["family"] == "col" and p["vec"] and p["window"] and p["nsplit"] == 1]
+           if p["family"] == "col" and p["vec"] and p["window"] and p["strip_units"] == 4]
     dom_ms, dom_b = [], []
     for lbl, b in dom:
         j = [o[0] for o in ops].index(lbl)
@@ -218,7 +218,7 @@ def main() -> int:
     achieved = avg_b / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "tvc::k_colw<1, true, 0, 4> (float32 short columns, LDS output window)",
+                "kernel": "tvc::k_colw<1, true, 0, 4, 4, true> (float32 column strips, LDS output window)",
                 "launches_per_step": len(dom), "avg_launch_ms": round(avg_ms, 4),
                 "avg_bytes_per_launch": int(avg_b)}
 

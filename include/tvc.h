@@ -130,7 +130,9 @@ int32_t tvc_contract(const tvc_tensor* A, int32_t mode, const void* x, void* y,
  * boundary), [7] full 16-byte vectors (or elements, scalar path) per row,
  * [8] 1 if each workgroup collects its outputs in an LDS window and writes
  * them in bursts (short contracted extents, where y is a sizeable share of
- * the traffic).
+ * the traffic), [9] family 1: column units per lane of the column-strip
+ * kernel (a wave per strip of 64 times that many units), 0 for wave groups
+ * sharing column tiles.
  * Returns TVC_OK or an argument error. */
 int32_t tvc_contract_plan(const tvc_tensor* A, int32_t mode, int32_t* info, int32_t n);
 
@@ -316,8 +318,10 @@ int32_t hopm_batch_profile(const void* ws, uint64_t* d_out, void* stream);
  * per compute unit; for family 3 a negative value turns the family off (the
  * dispatcher then uses families 0 and 2 for those shapes).  split_m (family
  * 1 only: 1, 2 or 4) is the number of wave groups sharing one column tile;
- * a negative split_m turns the LDS output window off (outputs are stored
- * as each tile finishes).  Values of 0 restore the built-in choice.  Process-wide; set it while no
+ * a negative split_m selects the plain kernels: no LDS output window in any
+ * family (outputs are stored as each task finishes) and no column strips
+ * (family 1 always uses wave groups sharing column tiles).  Values of 0
+ * restore the built-in choice.  Process-wide; set it while no
  * other thread is launching contractions.
  * ------------------------------------------------------------------------- */
 int32_t tvc_set_tuning(int32_t family, int32_t blocks_per_cu, int32_t split_m);

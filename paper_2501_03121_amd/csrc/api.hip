@@ -209,7 +209,7 @@ int32_t tvc_contract(const tvc_tensor* A, int32_t mode, const void* x, void* y, 
 int32_t tvc_set_tuning(int32_t family, int32_t blocks_per_cu, int32_t split_m) {
   if (family < 0 || family > 3) return fail(TVC_EINVAL, "family outside [0, 3]");
   if (family == kStage) tuning().stage_off = blocks_per_cu < 0;
-  if (family == kCol) tuning().win_off = split_m < 0;
+  if (family == kCol) tuning().win_off = tuning().strips_off = split_m < 0;
   if (split_m > 0 && split_m != 1 && split_m != 2 && split_m != 4)
     return fail(TVC_EINVAL, "split_m must be 1, 2 or 4");
   if (blocks_per_cu > 64) return fail(TVC_EINVAL, "blocks_per_cu above 64");
@@ -229,10 +229,11 @@ int32_t tvc_contract_plan(const tvc_tensor* A, int32_t mode, int32_t* info, int3
   const bool a4 = ((uintptr_t)A->data % 4) == 0;
   const bool a16 = ((uintptr_t)A->data % 16) == 0;
   TvcPlan p = plan_tvc(A->dtype, L, M, R, a4, true, a16);
-  const int32_t v[9] = {p.family, p.vec ? 1 : 0, p.splitm, p.nsplit, p.grid,
-                        (p.family == kCol || (p.family == kRow && p.lng)) ? 0 : (1 << p.glog),
-                        p.tail, (int32_t)std::min<i64>(p.upr, INT32_MAX), p.win ? 1 : 0};
-  for (int i = 0; i < n && i < 9; ++i) info[i] = v[i];
+  const int32_t v[10] = {p.family, p.vec ? 1 : 0, p.splitm, p.nsplit, p.grid,
+                         (p.family == kCol || (p.family == kRow && p.lng)) ? 0 : (1 << p.glog),
+                         p.tail, (int32_t)std::min<i64>(p.upr, INT32_MAX), p.win ? 1 : 0,
+                         (p.family == kCol && p.strips) ? p.cpt : 0};
+  for (int i = 0; i < n && i < 10; ++i) info[i] = v[i];
   return TVC_OK;
 }
 

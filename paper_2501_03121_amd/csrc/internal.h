@@ -38,13 +38,16 @@ struct TvcPlan {
   i64 sb = 0;            // kStage: slabs per LDS block
   int stage_vb = 0;      // kStage: 16 = 16-byte LDS reads, 0 = one element per read
   bool win = false;      // outputs written through an LDS window in bursts
-  int wv = 4;            // waves per workgroup of the windowed column and slab kernels
+  int wv = 4;            // waves per workgroup of the column-strip and windowed slab kernels
+  bool strips = false;   // kCol: column strips, a wave per strip (k_colw)
+  int cpt = 1;           // kCol strips: column units per lane
 };
 
 struct Tuning {
   int blocks_per_cu[4] = {0, 0, 0, 0};
   bool stage_off = false;  // never pick the LDS-staged family
   bool win_off = false;    // never write outputs through an LDS window
+  bool strips_off = false; // never use the column-strip kernel
   int split_m = 0;
 };
 Tuning& tuning();

@@ -58,6 +58,7 @@ struct ColwShape {
   static constexpr int kUnroll = 32 / WV;
 };
 constexpr int kColwMaxThreads = 8 * kWave;
+constexpr int kColwMaxM = 4096;  // weights staged in LDS by the column-strip kernel
 // Short rows with the window: a row-group reduction per row, so more waves
 // per workgroup (1024 threads) to hide its latency, 8 rows per lane per task.
 #ifndef TVC_ROWSW_UNROLL
@@ -496,99 +497,143 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a)
   }
 }
 
-// ------------------------------------------------------ kCol, short columns
-// Short contracted extents, outputs through the LDS window: a wave owns a
-// strip of 64 column units of one slab and streams all M rows of it, UN
-// loads in flight (no combine across waves, so no barrier per task).  The
-// strips of a workgroup's contiguous range go to its four waves in rounds;
-// a round's outputs are one stretch of y, and the window is flushed between
-// rounds when the next round's stretch would not fit.  The M weights are
-// copied to LDS once, so the row loop issues no vector loads but A's.
-template <int DT, bool VEC, int ROLE, int WV>
+// ------------------------------------------------------ kCol, column strips
+// A wave owns a strip of CPT * 64 column units of one slab (lane owns units
+// lane, lane + 64, ...) and streams all M rows of it, UN loads in flight: a
+// batch is UN / CPT rows of CPT * 1 KB contiguous pieces.  No combine across
+// waves, so no barrier per task; the M weights are staged in LDS once.
+// Several units per lane matter when rows are a power-of-two number of MB
+// apart: loads of one column unit down 8 such rows fall on few HBM channels
+// (measured on gfx950, 1000 rows 4 MB apart: 5.7 TB/s with one unit per
+// lane, 7.1 TB/s with four or with a 4 KB pad between rows).  A lane's units
+// past the row end re-read the row's last unit and are not stored, so every
+// load is unconditional.  With WIN (short M, where y is a sizeable share of
+// the traffic) the strips of a workgroup's contiguous range go to its waves
+// in rounds whose outputs are one stretch of y, collected in the LDS window;
+// without it every output is stored as its strip finishes.
+template <int DT, bool VEC, int ROLE, int WV, int CPT, bool WIN>
 __global__ __launch_bounds__(ColwShape<WV>::kThreads) void k_colw(ColArgs<typename St<DT>::Acc> a) {
   typedef typename St<DT>::Acc Acc;
+  typedef typename St<DT>::T T;
   typedef Unit<DT, VEC> U;
   constexpr int EU = U::EU;
   constexpr int NT = ColwShape<WV>::kThreads;
   constexpr int UN = ColwShape<WV>::kUnroll;
-  constexpr int WPB = WV;
-  constexpr i64 SW = (i64)kWave * EU;  // elements of y per strip
-  __shared__ __align__(16) Acc win[Win<Acc>::kElems];
-  __shared__ Acc wl[kWinMaxM];
+  constexpr int RPB = UN / CPT;               // rows per batch of loads
+  static_assert(RPB >= 1 && RPB * CPT == UN, "CPT must divide the loads in flight");
+  constexpr i64 SWU = (i64)kWave * CPT;       // column units per strip
+  constexpr i64 SW = SWU * EU;                // elements of y per strip
+  __shared__ __align__(16) Acc win[WIN ? Win<Acc>::kElems : 1];
+  __shared__ Acc wl[WIN ? kWinMaxM : kColwMaxM];
   const int lane = lane_id();
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int M = (int)a.M;
   for (int i = threadIdx.x; i < M; i += NT) wl[i] = a.w[i];
   __syncthreads();
-  const TaskRange tr = block_range(a.L * a.ctiles);
+  const i64 rs = a.R * (i64)sizeof(T);  // row stride, bytes
+  const TaskRange tr = WIN ? block_range(a.L * a.ctiles) : TaskRange{(i64)blockIdx.x * WV, a.L * a.ctiles,
+                                                                     (i64)gridDim.x * WV};
   i64 org = 0, wbase = 0, wend = 0;
-  for (i64 t0 = tr.begin; t0 < tr.end; t0 += WPB) {
-    const i64 tlast = min(t0 + WPB, tr.end) - 1;
-    i64 l0, c0, l1, c1;
-    divmod(t0, a.ctiles, l0, c0);
-    divmod(tlast, a.ctiles, l1, c1);
-    const i64 ys = l0 * a.R + c0 * SW;
-    const i64 ye = l1 * a.R + min(a.R, (c1 + 1) * SW);
-    if (t0 == tr.begin) {
-      wbase = ys;
-      org = win_origin(a.y, ys);
-    } else if (ye - org > Win<Acc>::kElems) {
-      win_flush<Acc, NT>(a.y, win, org, wbase, ys);
-      wbase = ys;
-      org = win_origin(a.y, ys);
+  for (i64 t0 = tr.begin; t0 < tr.end; t0 += (WIN ? WV : tr.step)) {
+    i64 t = t0 + wv;
+    if constexpr (WIN) {
+      const i64 tlast = min(t0 + WV, tr.end) - 1;
+      i64 l0, c0, l1, c1;
+      divmod(t0, a.ctiles, l0, c0);
+      divmod(tlast, a.ctiles, l1, c1);
+      const i64 ys = l0 * a.R + c0 * SW;
+      const i64 ye = l1 * a.R + min(a.R, (c1 + 1) * SW);
+      if (t0 == tr.begin) {
+        wbase = ys;
+        org = win_origin(a.y, ys);
+      } else if (ye - org > Win<Acc>::kElems) {
+        win_flush<Acc, NT>(a.y, win, org, wbase, ys);
+        wbase = ys;
+        org = win_origin(a.y, ys);
+      }
+      wend = ye;
+      if (t > tlast) continue;
+    } else {
+      if (t >= tr.end) break;
     }
-    wend = ye;
-    const i64 t = t0 + wv;
-    if (t > tlast) continue;
     i64 l, ct;
     divmod(t, a.ctiles, l, ct);
-    const i64 c = ct * kWave + lane;
-    const bool tl = a.tail > 0 && c == a.upr;
-    if (!(c < a.upr || tl)) continue;
-    const i64 eo = tl ? a.R - EU : c * EU;
-    const char* base = (const char*)a.A + (l * a.M * a.R + eo) * (i64)sizeof(typename St<DT>::T);
-    const i64 rs = a.R * (i64)sizeof(typename St<DT>::T);  // row stride, bytes
-    Acc acc[EU];
+    const char* row0 = (const char*)a.A + l * a.M * a.R * (i64)sizeof(T);
+    i64 eo[CPT];
+    bool act[CPT], tl[CPT];
 #pragma unroll
-    for (int e = 0; e < EU; ++e) acc[e] = (Acc)0;
-    int m = 0;
-    for (; m + UN <= M; m += UN) {
-      typename U::Raw raw[UN];
-#pragma unroll
-      for (int k = 0; k < UN; ++k) raw[k] = U::load(base + (i64)(m + k) * rs, 0);
-#pragma unroll
-      for (int k = 0; k < UN; ++k) {
-        Acc v[EU];
-        U::unpack(raw[k], v);
-        const Acc wk = wl[m + k];
-#pragma unroll
-        for (int e = 0; e < EU; ++e) acc[e] = fma(v[e], wk, acc[e]);
-      }
+    for (int j = 0; j < CPT; ++j) {
+      const i64 c = ct * SWU + j * kWave + lane;
+      tl[j] = a.tail > 0 && c == a.upr;
+      act[j] = c < a.upr || tl[j];
+      eo[j] = c < a.upr ? c * EU : a.R - EU;
     }
-    if (m < M) {
-      // the last M mod UN rows, loads issued together (M is uniform)
-      typename U::Raw raw[UN - 1];
+    Acc acc[CPT][EU];
 #pragma unroll
-      for (int k = 0; k < UN - 1; ++k) raw[k] = m + k < M ? U::load(base + (i64)(m + k) * rs, 0) : U::zero();
+    for (int j = 0; j < CPT; ++j)
 #pragma unroll
-      for (int k = 0; k < UN - 1; ++k) {
-        if (m + k < M) {
+      for (int e = 0; e < EU; ++e) acc[j][e] = (Acc)0;
+    int m = 0;
+    for (; m + RPB <= M; m += RPB) {
+      typename U::Raw raw[RPB][CPT];
+#pragma unroll
+      for (int q = 0; q < RPB; ++q)
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) raw[q][j] = U::load(row0 + (i64)(m + q) * rs, eo[j]);
+#pragma unroll
+      for (int q = 0; q < RPB; ++q) {
+        const Acc wk = wl[m + q];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
           Acc v[EU];
-          U::unpack(raw[k], v);
-          const Acc wk = wl[m + k];
+          U::unpack(raw[q][j], v);
 #pragma unroll
-          for (int e = 0; e < EU; ++e) acc[e] = fma(v[e], wk, acc[e]);
+          for (int e = 0; e < EU; ++e) acc[j][e] = fma(v[e], wk, acc[j][e]);
         }
       }
     }
-    const i64 idx = l * a.R + eo;
-    const int from = tl ? EU - a.tail : 0;
-    Acc* wp = win + (idx - org);
+    if constexpr (RPB > 1) {
+      if (m < M) {
+        // the last M mod RPB rows, loads issued together (M is uniform)
+        typename U::Raw raw[RPB - 1][CPT];
 #pragma unroll
-    for (int e = 0; e < EU; ++e)
-      if (e >= from) wp[e] = epilogue(acc[e], a.y, idx + e, l, a.alpha, a.beta, a.oscale, a.odiv);
+        for (int q = 0; q < RPB - 1; ++q)
+#pragma unroll
+          for (int j = 0; j < CPT; ++j)
+            raw[q][j] = m + q < M ? U::load(row0 + (i64)(m + q) * rs, eo[j]) : U::zero();
+#pragma unroll
+        for (int q = 0; q < RPB - 1; ++q) {
+          if (m + q < M) {
+            const Acc wk = wl[m + q];
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+              Acc v[EU];
+              U::unpack(raw[q][j], v);
+#pragma unroll
+              for (int e = 0; e < EU; ++e) acc[j][e] = fma(v[e], wk, acc[j][e]);
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (!act[j]) continue;
+      const i64 idx = l * a.R + eo[j];
+      const int from = tl[j] ? EU - a.tail : 0;
+      if constexpr (WIN) {
+        Acc* wp = win + (idx - org);
+#pragma unroll
+        for (int e = 0; e < EU; ++e)
+          if (e >= from) wp[e] = epilogue(acc[j][e], a.y, idx + e, l, a.alpha, a.beta, a.oscale, a.odiv);
+      } else {
+        store_epilogue<Acc, EU>(acc[j], a.y, idx, l, a.alpha, a.beta, a.oscale, a.odiv, from);
+      }
+    }
   }
-  if (tr.begin < tr.end) win_flush<Acc, NT>(a.y, win, org, wbase, wend);
+  if constexpr (WIN) {
+    if (tr.begin < tr.end) win_flush<Acc, NT>(a.y, win, org, wbase, wend);
+  }
 }
 
 // ---------------------------------------------------------------- kSlab
@@ -1164,16 +1209,35 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
       }
       p.tasks = tasks * p.nsplit;
       p.grid = grid_for(p.tasks, kCol, 4);
-      // Short columns (no split of M): a wave per 64-unit strip, outputs
-      // through the LDS window, as many workgroups per CU as windows fit.
-      if (p.nsplit == 1 && win_ok(M, L * cdiv(nu, kWave))) {
-        p.win = true;
-        p.wv = M < 32 ? 8 : 4;
-        p.tasks = L * cdiv(nu, kWave);
-        p.grid = grid_for(cdiv(p.tasks, p.wv), kCol, kWinBlocksPerCu);
-#ifdef TVC_WIN_GRID_SUB
-        p.grid = std::max(1, p.grid - TVC_WIN_GRID_SUB);
-#endif
+      // Column strips (no split of M, weights fit in LDS): the widest strip
+      // up to 4 units per lane that the rows fill and that still gives a
+      // busy wave per SIMD (with the window: several rounds per workgroup);
+      // short M also writes through the LDS window (one workgroup per CU
+      // beside it), a round of strips being at most half the window.
+      if (p.nsplit == 1 && M <= kColwMaxM && !tuning().strips_off) {
+        const bool win = win_ok(M, L * cdiv(nu, kWave));
+        // 8 waves of 4 loads for short strips (M < 32) and, with the window
+        // (one workgroup per CU), for E4M3, whose 16 conversions and FMAs per
+        // load need more waves to hide them (32^6 modes 1-3: 54-58 -> 61-66%)
+        const int wv = (M < 32 || (win && epv >= 16)) ? 8 : 4;
+        // with the window, several units per lane only where rows are a
+        // multiple of 64 KB apart (measured: 32^6 mode 1, 4 MB rows, 75 -> 79%;
+        // 4 KB rows lose 4%)
+        const int cmax = !win ? 4 : ((R * b) % 65536 == 0 ? 4 : 1);
+        for (int cpt = cmax; cpt >= 1; cpt /= 2) {
+          const i64 strips = L * cdiv(nu, (i64)kWave * cpt);
+          const bool fits = !win || (i64)wv * kWave * cpt * epv * (i64)ab <= kWinBytes / 2;
+          const i64 need = (win ? 16 : wv) * (i64)device_cus();
+          if ((cpt == 1 || nu >= (i64)kWave * cpt) && strips >= need && fits) {
+            p.strips = true;
+            p.win = win;
+            p.wv = wv;
+            p.cpt = cpt;
+            p.tasks = strips;
+            p.grid = grid_for(cdiv(strips, wv), kCol, win ? kWinBlocksPerCu : 4);
+            break;
+          }
+        }
       }
     } else {
       p.family = kSlab;
@@ -1203,6 +1267,33 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
 }
 
 namespace {
+
+// The column-strip kernel for a plan: vector or scalar units, waves per
+// workgroup, column units per lane, window.
+template <int DT, int ROLE, bool VEC, int WV, int CPT>
+void launch_colw_c(const TvcPlan& p, dim3 grd, hipStream_t st, const ColArgs<typename St<DT>::Acc>& a) {
+  const dim3 blk(ColwShape<WV>::kThreads);
+  if (p.win) hipLaunchKernelGGL((k_colw<DT, VEC, ROLE, WV, CPT, true>), grd, blk, 0, st, a);
+  else hipLaunchKernelGGL((k_colw<DT, VEC, ROLE, WV, CPT, false>), grd, blk, 0, st, a);
+}
+
+template <int DT, int ROLE, bool VEC, int WV>
+void launch_colw_w(const TvcPlan& p, dim3 grd, hipStream_t st, const ColArgs<typename St<DT>::Acc>& a) {
+  if (p.cpt == 4) launch_colw_c<DT, ROLE, VEC, WV, 4>(p, grd, st, a);
+  else if (p.cpt == 2) launch_colw_c<DT, ROLE, VEC, WV, 2>(p, grd, st, a);
+  else launch_colw_c<DT, ROLE, VEC, WV, 1>(p, grd, st, a);
+}
+
+template <int DT, int ROLE>
+void launch_colw(const TvcPlan& p, dim3 grd, hipStream_t st, const ColArgs<typename St<DT>::Acc>& a) {
+  if (p.vec) {
+    if (p.wv == 8) launch_colw_w<DT, ROLE, true, 8>(p, grd, st, a);
+    else launch_colw_w<DT, ROLE, true, 4>(p, grd, st, a);
+  } else {
+    if (p.wv == 8) launch_colw_w<DT, ROLE, false, 8>(p, grd, st, a);
+    else launch_colw_w<DT, ROLE, false, 4>(p, grd, st, a);
+  }
+}
 
 template <int DT, int ROLE>
 hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, double alpha,
@@ -1245,21 +1336,13 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
       else hipLaunchKernelGGL((k_row_short<DT, false, ROLE>), grd, blk, 0, st, a);
     }
   } else {
-    const i64 tc = (p.family == kCol && p.win) ? kWave : kBlock / p.splitm;
+    const i64 tc = (p.family == kCol && p.strips) ? (i64)kWave * p.cpt : kBlock / p.splitm;
     const i64 nu = p.upr + (p.tail > 0 ? 1 : 0);
     ColArgs<Acc> a{A, w, y, part, L, M, p.upr, R, (nu + tc - 1) / tc, p.chunk, p.nsplit,
                    p.glog, (Acc)alpha, (Acc)beta, oscale, odiv, p.tail};
     if (p.family == kCol) {
-      if (p.win) {
-        if (p.wv == 8) {
-          const dim3 wblk(ColwShape<8>::kThreads);
-          if (p.vec) hipLaunchKernelGGL((k_colw<DT, true, ROLE, 8>), grd, wblk, 0, st, a);
-          else hipLaunchKernelGGL((k_colw<DT, false, ROLE, 8>), grd, wblk, 0, st, a);
-        } else {
-          const dim3 wblk(ColwShape<4>::kThreads);
-          if (p.vec) hipLaunchKernelGGL((k_colw<DT, true, ROLE, 4>), grd, wblk, 0, st, a);
-          else hipLaunchKernelGGL((k_colw<DT, false, ROLE, 4>), grd, wblk, 0, st, a);
-        }
+      if (p.strips) {
+        launch_colw<DT, ROLE>(p, grd, st, a);
       } else if (p.vec) {
         if (p.splitm == 4) hipLaunchKernelGGL((k_col<DT, true, 4, ROLE>), grd, blk, 0, st, a);
         else if (p.splitm == 2) hipLaunchKernelGGL((k_col<DT, true, 2, ROLE>), grd, blk, 0, st, a);

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 import paper_2501_03121_amd as tvc
+from oracle import quant as Q
 from oracle import tvc as O
 from paper_2501_03121_amd import synth
 from _util import TOL, host, stored_tensor, vec
@@ -314,3 +315,53 @@ def test_windowed_rows_and_slabs(dev, fmt):
         assert torch.equal(a, b), (fmt, dims, k)
         ref = O.tvc(exact, xh, k, alpha=0.5, beta=-1.25, y=y0)
         assert O.rel_err(host(a), ref) <= TOL[fmt], (fmt, dims, k)
+
+
+# Column strips without the window (M above 256): a wave streams all M rows
+# of a strip of 64, 128 or 256 column units.  Large enough for every wave to
+# get a strip, so the tensors are made on the device and outputs are checked
+# one by one against the oracle's definition on sampled columns, the ragged
+# last columns included.
+def _device_stored(dims, fmt, seed, dev):
+    A32 = synth.device_normal(dims, seed, dev)
+    if fmt == "f32":
+        return A32, None, lambda idx: A32[idx].double().cpu().numpy()
+    if fmt == "f64":
+        A = A32.double()
+        return A, None, lambda idx: A[idx].cpu().numpy()
+    A, S = tvc.quantize(A32, fmt)
+    if fmt == "e4m3":
+        def exact(idx):
+            codes = A[idx].view(torch.uint8).cpu().numpy()
+            return Q.e4m3_to_f64(codes) * float(S[idx[0]])
+        return A, S, exact
+    raw = lambda idx: A[idx].view(torch.int16).cpu().numpy().view(np.uint16)
+    conv = Q.bf16_to_f64 if fmt == "bf16" else Q.f16_to_f64
+    return A, None, lambda idx: conv(raw(idx))
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_column_strips(dev, fmt):
+    e = EPV[fmt]
+    # strips of 4, 2 and 1 units per lane in float32 (fewer strips as the
+    # tensor shrinks); the smaller cases may fall back to the split column
+    # kernel in the narrow formats, which must agree all the same
+    for i, dims in enumerate([(1, 260, (1 << 20) + e // 2), (4, 260, (1 << 17) + e // 2),
+                              (16, 260, (1 << 14) + e // 2)]):
+        A, S, exact = _device_stored(dims, fmt, 41, dev)
+        p = tvc.contract_plan(A, 1, scale=S)
+        assert p["family"] == "col" and not p["window"], (fmt, dims, p)
+        assert i > 0 or p["strip_units"] > 0, (fmt, dims, p)
+        if fmt == "f32":
+            assert p["strip_units"] == (4, 2, 1)[i], (dims, p)
+        x, xh = vec(dims[1], 42, fmt, dev)
+        yh = host(tvc.contract(A, x, 1, scale=S))
+        xs = xh.astype(np.float64)
+        g = synth.rng(43)
+        cols = np.concatenate([g.integers(0, dims[2], 48), np.arange(dims[2] - 5, dims[2])])
+        for l in (0, dims[0] - 1):
+            for j in cols:
+                a = exact((l, slice(None), int(j)))
+                want = float(a @ xs)
+                bound = TOL[fmt] * float(np.abs(a) @ np.abs(xs))
+                assert abs(float(yh[l, j]) - want) <= bound, (fmt, dims, l, j)
