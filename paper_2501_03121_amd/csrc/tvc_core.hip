@@ -872,8 +872,27 @@ __global__ __launch_bounds__(kRowswThreads) void k_rowsw(RowArgs<typename St<DT>
 // narrow formats lose more to the wider groups' reductions and LDS bank
 // conflicts than they gain, so they read one element at a time).
 constexpr int kStageBytes = 32768;
-constexpr int kStageVecs = kStageBytes / 16;
-constexpr int kStagePer = kStageVecs / kBlock;
+// With the output window: staging buffer, window and threads per workgroup,
+// and workgroups per CU.  The staged kernel needs several blocks in flight
+// per CU more than long bursts: measured on gfx950 over Table 1's staged
+// modes, one 1024-thread workgroup with a 96 KB window per CU lost 10-20
+// points, four 256-thread workgroups with 8 KB windows gained 0-5.
+#ifndef TVC_STAGEW_THREADS
+#define TVC_STAGEW_THREADS 256
+#endif
+#ifndef TVC_STAGEW_BYTES
+#define TVC_STAGEW_BYTES 32768
+#endif
+#ifndef TVC_STAGEW_WIN
+#define TVC_STAGEW_WIN 8192
+#endif
+#ifndef TVC_STAGEW_BPC
+#define TVC_STAGEW_BPC 4
+#endif
+constexpr int kStagewThreads = TVC_STAGEW_THREADS;
+constexpr int kStagewBytes = TVC_STAGEW_BYTES;
+constexpr int kStageWinBytes = TVC_STAGEW_WIN;
+constexpr int kStagewBpc = TVC_STAGEW_BPC;
 
 template <typename Acc>
 struct StageArgs {
@@ -884,18 +903,22 @@ struct StageArgs {
   const float* oscale; i64 odiv;
 };
 
-template <int DT, int ROLE, int VB>
-__global__ __launch_bounds__(kBlock) void k_stage(StageArgs<typename St<DT>::Acc> a) {
+template <int DT, int ROLE, int VB, int NT, bool WIN>
+__global__ __launch_bounds__(NT) void k_stage(StageArgs<typename St<DT>::Acc> a) {
   typedef typename St<DT>::Acc Acc;
   typedef typename St<DT>::T T;
   constexpr int EB = (int)sizeof(T);
   constexpr int VE = VB == 0 ? 1 : VB / EB;   // columns per output group
+  constexpr int kStageVecs = (WIN ? kStagewBytes : kStageBytes) / 16;
+  constexpr int PER = kStageVecs / NT;        // 16-byte loads per thread per block
+  constexpr int WE = kStageWinBytes / (int)sizeof(Acc);
   __shared__ uint4 lds[kStageVecs];
+  __shared__ __align__(16) Acc win[WIN ? WE : 1];
   const int tid = threadIdx.x;
   const i64 E = a.M * a.R;
   const int G = 1 << a.glog;
   const int sub = tid & (G - 1);
-  uint4 r[kStagePer];
+  uint4 r[PER];
   i64 nvec = 0;
   auto issue = [&](i64 b) {
     const i64 l0 = b * a.sb;
@@ -903,20 +926,24 @@ __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<typename St<DT>::Acc
     nvec = ns * E * EB / 16;
     const char* src = (const char*)a.A + l0 * E * EB;
 #pragma unroll
-    for (int k = 0; k < kStagePer; ++k) {
-      const i64 v = tid + (i64)k * kBlock;
+    for (int k = 0; k < PER; ++k) {
+      const i64 v = tid + (i64)k * NT;
       r[k] = v < nvec ? stream_load16(src + v * 16) : uint4{0u, 0u, 0u, 0u};
     }
   };
-  i64 b = blockIdx.x;
-  if (b < a.nblocks) issue(b);
-  for (; b < a.nblocks; b += gridDim.x) {
+  // with the window a workgroup takes a contiguous range of blocks (their
+  // outputs are one stretch of y), else blocks are dealt round-robin
+  const TaskRange tr = WIN ? block_range(a.nblocks) : block_tasks(a.nblocks);
+  i64 org = 0, wbase = 0, wend = 0;
+  i64 b = tr.begin;
+  if (b < tr.end) issue(b);
+  for (; b < tr.end; b += tr.step) {
     const i64 l0 = b * a.sb;
     const i64 ns = min(a.sb, a.L - l0);
     __syncthreads();  // the previous block's outputs no longer read the LDS
 #pragma unroll
-    for (int k = 0; k < kStagePer; ++k) {
-      const i64 v = tid + (i64)k * kBlock;
+    for (int k = 0; k < PER; ++k) {
+      const i64 v = tid + (i64)k * NT;
       if (v < nvec) lds[v] = r[k];
     }
     {  // bytes of the last block after its final whole 16-byte vector
@@ -925,11 +952,23 @@ __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<typename St<DT>::Acc
       if (e0 + tid < e1) ((T*)lds)[e0 + tid] = src[e0 + tid];
     }
     __syncthreads();
-    if (b + gridDim.x < a.nblocks) issue(b + gridDim.x);
+    if (b + tr.step < tr.end) issue(b + tr.step);
+    if constexpr (WIN) {
+      const i64 ys = l0 * a.R, ye = (l0 + ns) * a.R;
+      if (b == tr.begin) {
+        wbase = ys;
+        org = win_origin(a.y, ys);
+      } else if (ye - org > WE) {
+        win_flush<Acc, NT>(a.y, win, org, wbase, ys);
+        wbase = ys;
+        org = win_origin(a.y, ys);
+      }
+      wend = ye;
+    }
     const i64 Rv = a.R / VE;          // output groups per slab row
     const i64 nout = ns * Rv;
     const T* sl = (const T*)lds;
-    for (i64 o = tid >> a.glog; o < a.sb * Rv; o += kBlock >> a.glog) {
+    for (i64 o = tid >> a.glog; o < a.sb * Rv; o += NT >> a.glog) {
       Acc acc0[VE], acc1[VE];
 #pragma unroll
       for (int v = 0; v < VE; ++v) acc0[v] = acc1[v] = (Acc)0;
@@ -962,10 +1001,15 @@ __global__ __launch_bounds__(kBlock) void k_stage(StageArgs<typename St<DT>::Acc
         for (int off = G >> 1; off >= 1; off >>= 1) t += shfl_xor(t, off);
         if (sub == 0 && o < nout) {
           const i64 idx = l0 * a.R + o * VE + v;
-          a.y[idx] = epilogue(t, a.y, idx, l0 + ls, a.alpha, a.beta, a.oscale, a.odiv);
+          const Acc out = epilogue(t, a.y, idx, l0 + ls, a.alpha, a.beta, a.oscale, a.odiv);
+          if constexpr (WIN) win[idx - org] = out;
+          else a.y[idx] = out;
         }
       }
     }
+  }
+  if constexpr (WIN) {
+    if (tr.begin < tr.end) win_flush<Acc, NT>(a.y, win, org, wbase, wend);
   }
 }
 
@@ -1110,24 +1154,31 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
                             : (sbytes <= 4096 && nu <= 32 && (p.tail > 0 || !pow2 || nu <= 2));
   if (a16 && small && !tuning().stage_off) {
     const i64 q = 16 / gcd_(16, sbytes);
-    const i64 sb = (kStageBytes / sbytes) / q * q;
+    // with many blocks, outputs through the LDS window (a block's outputs at
+    // most half of it), in blocks of the window variant's staging size
+    const i64 sbw = (kStagewBytes / sbytes) / q * q;
+    const bool win = kWinOn && !tuning().win_off && sbw >= 1 &&
+                     cdiv(L, sbw) >= 4 * (i64)device_cus() && sbw * R * (i64)ab <= kStageWinBytes / 2;
+    const i64 sb = win ? sbw : (kStageBytes / sbytes) / q * q;
     if (sb >= 1) {
       p.family = kStage;
+      p.win = win;
       p.sb = sb;
       p.vec = true;
       // LDS word per read: 16 bytes for 4- and 8-byte elements when a slab
       // row is a whole number of them, else one element
       p.stage_vb = (b >= 4 && (R * b) % 16 == 0) ? 16 : 0;
       const i64 ve = p.stage_vb == 0 ? 1 : p.stage_vb / b;
-      // lanes per output group: as many as keep all 256 threads busy
+      p.nsplit = 1;
+      p.tasks = cdiv(L, sb);
+      p.grid = grid_for(p.tasks, kStage, p.win ? kStagewBpc : 4);
+      const int nt = p.win ? kStagewThreads : kBlock;
+      // lanes per output group: as many as keep all threads busy
       // (measured: a whole wave per row serialises the reductions)
       const i64 outs = std::max<i64>(sb * R / ve, 1);
       int g = 0;
-      while (g < 6 && ((i64)2 << g) * outs <= kBlock && ((i64)1 << g) < M) ++g;
+      while (g < 6 && ((i64)2 << g) * outs <= nt && ((i64)1 << g) < M) ++g;
       p.glog = g;
-      p.nsplit = 1;
-      p.tasks = cdiv(L, sb);
-      p.grid = grid_for(p.tasks, kStage, 4);
       p.part_bytes = 0;
       return p;
     }
@@ -1307,9 +1358,17 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
   const dim3 grd(p.grid);
   if (p.family == kStage) {
     StageArgs<Acc> a{A, w, y, L, M, R, p.sb, p.tasks, p.glog, (Acc)alpha, (Acc)beta, oscale, odiv};
-    if (p.stage_vb == 16 && (DT == TVC_F32 || DT == TVC_F64))
-      hipLaunchKernelGGL((k_stage<DT, ROLE, (DT == TVC_F32 || DT == TVC_F64) ? 16 : 0>), grd, blk, 0, st, a);
-    else hipLaunchKernelGGL((k_stage<DT, ROLE, 0>), grd, blk, 0, st, a);
+    constexpr int VW = (DT == TVC_F32 || DT == TVC_F64) ? 16 : 0;
+    if (p.win) {
+      const dim3 wblk(kStagewThreads);
+      if (p.stage_vb == 16 && VW == 16)
+        hipLaunchKernelGGL((k_stage<DT, ROLE, VW, kStagewThreads, true>), grd, wblk, 0, st, a);
+      else hipLaunchKernelGGL((k_stage<DT, ROLE, 0, kStagewThreads, true>), grd, wblk, 0, st, a);
+    } else {
+      if (p.stage_vb == 16 && VW == 16)
+        hipLaunchKernelGGL((k_stage<DT, ROLE, VW, kBlock, false>), grd, blk, 0, st, a);
+      else hipLaunchKernelGGL((k_stage<DT, ROLE, 0, kBlock, false>), grd, blk, 0, st, a);
+    }
     return hipGetLastError();
   }
   if (p.family == kRow) {
