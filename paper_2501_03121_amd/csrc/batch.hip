@@ -322,8 +322,7 @@ __device__ void phase_p1(const BatchDesc& D, const InstLayout& L, float* s, int 
     }
 #pragma unroll
     for (int j = 0; j < RU; ++j) {
-      float v = acc[j];
-      for (int off = G >> 1; off >= 1; off >>= 1) v += shfl_xor(v, off);
+      const float v = group_sum(acc[j], g);
       const int64_t row = rb + (int64_t)j * P + rsub;
       if (sub == 0 && row < r1) M[row] = v;
     }
