@@ -266,9 +266,22 @@ __device__ __forceinline__ const char* uniform_ptr(const void* p) {
 // alignment (row starts are 4-byte aligned), the ragged end of a row read as
 // one more unit over its last 4 columns with the overlap dropped.
 
+// Outputs of a tile are collected in an LDS window of kBWin floats and
+// written in bursts: small stores spread through a read stream cost HBM
+// several times their bytes (pass-1 rows of 16-256 values make M up to
+// 1/16 of the tile's bytes, pass-2 partials of order-5 instances up to 1/25).
+constexpr int kBWin = 8192;
+
+__device__ __forceinline__ void bwin_flush(float* dst, const float* win, int n) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBThreads) dst[i] = win[i];
+  __syncthreads();
+}
+
 // P1: M[row] = sum_c A[row, c] * w1[c].  G lanes per row (a power of two,
-// at most 64), several row groups in flight per wave.
-__device__ void phase_p1(const BatchDesc& D, const InstLayout& L, float* s, int tile) {
+// at most 64), several row groups in flight per wave; the rows of a tile go
+// in chunks of kBWin through the window.
+__device__ void phase_p1(const BatchDesc& D, const InstLayout& L, float* s, int tile, float* win) {
   const int64_t R = L.R1;
   const int64_t r0 = (int64_t)tile * D.tile_rows1;
   const int64_t r1 = min(L.n01, r0 + D.tile_rows1);
@@ -295,44 +308,50 @@ __device__ void phase_p1(const BatchDesc& D, const InstLayout& L, float* s, int 
   const int wave = threadIdx.x / kWave;
   // the tile is far below 2^31 bytes: lanes address it with 32-bit offsets
   const char* tbase = uniform_ptr(D.A + r0 * R);
-  for (int64_t rb = r0 + (int64_t)wave * P * RU; rb < r1; rb += (int64_t)NW * P * RU) {
-    float acc[RU];
+  for (int64_t c0 = r0; c0 < r1; c0 += kBWin) {
+    const int64_t c1 = min(r1, c0 + kBWin);
+    for (int64_t rb = c0 + (int64_t)wave * P * RU; rb < c1; rb += (int64_t)NW * P * RU) {
+      float acc[RU];
 #pragma unroll
-    for (int j = 0; j < RU; ++j) acc[j] = 0.f;
-    for (int64_t u = sub; u < nu; u += G) {
-      const bool tl = T != 0 && u == U;
-      const int64_t e = tl ? R - 4 : u * 4;
-      const int from = tl ? 4 - T : 0;
-      float wt[4];
-      load_w<float, 4>(w, e, wt);
-      uint4 raw[RU];
+      for (int j = 0; j < RU; ++j) acc[j] = 0.f;
+      for (int64_t u = sub; u < nu; u += G) {
+        const bool tl = T != 0 && u == U;
+        const int64_t e = tl ? R - 4 : u * 4;
+        const int from = tl ? 4 - T : 0;
+        float wt[4];
+        load_w<float, 4>(w, e, wt);
+        uint4 raw[RU];
+#pragma unroll
+        for (int j = 0; j < RU; ++j) {
+          const int64_t row = rb + (int64_t)j * P + rsub;
+          raw[j] = row < c1 ? stream_load16(tbase + (uint32_t)(((row - r0) * R + e) * 4)) : uint4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int j = 0; j < RU; ++j) {
+          float v[4];
+          unpack16<TVC_F32>(raw[j], v);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (q >= from) acc[j] = fmaf(v[q], wt[q], acc[j]);
+        }
+      }
 #pragma unroll
       for (int j = 0; j < RU; ++j) {
+        const float v = group_sum(acc[j], g);
         const int64_t row = rb + (int64_t)j * P + rsub;
-        raw[j] = row < r1 ? stream_load16(tbase + (uint32_t)(((row - r0) * R + e) * 4)) : uint4{0u, 0u, 0u, 0u};
-      }
-#pragma unroll
-      for (int j = 0; j < RU; ++j) {
-        float v[4];
-        unpack16<TVC_F32>(raw[j], v);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (q >= from) acc[j] = fmaf(v[q], wt[q], acc[j]);
+        if (sub == 0 && row < c1) win[row - c0] = v;
       }
     }
-#pragma unroll
-    for (int j = 0; j < RU; ++j) {
-      const float v = group_sum(acc[j], g);
-      const int64_t row = rb + (int64_t)j * P + rsub;
-      if (sub == 0 && row < r1) M[row] = v;
-    }
+    bwin_flush(M + c0, win, (int)(c1 - c0));
   }
 }
 
 // P2: part[c] = sum over the tile's rows of w2[row] * A[row, c].  TC threads
 // per row own 16-byte column units, the 256/TC row groups of the workgroup
-// stream interleaved rows and combine in LDS in a fixed order.
-__device__ void phase_p2(const BatchDesc& D, const InstLayout& L, float* s, int tile, float* lds) {
+// stream interleaved rows and combine in LDS in a fixed order; the partials
+// go in chunks of kBWin columns through the window.
+__device__ void phase_p2(const BatchDesc& D, const InstLayout& L, float* s, int tile, float* lds,
+                         float* win) {
   const int64_t R = L.R1;
   const int64_t r0 = (int64_t)tile * D.tile_rows2;
   const int64_t r1 = min(L.n01, r0 + D.tile_rows2);
@@ -355,7 +374,12 @@ __device__ void phase_p2(const BatchDesc& D, const InstLayout& L, float* s, int 
   const int TC = 1 << g, RG = kBThreads >> g;
   const int tc = threadIdx.x & (TC - 1), rg = threadIdx.x >> g;
   const char* tbase = uniform_ptr(D.A + r0 * R);   // 32-bit lane offsets below
+  int64_t wc0 = 0;  // first column held by the window
   for (int64_t cb = 0; cb < nu; cb += TC) {
+    if ((cb + TC) * 4 - wc0 > kBWin) {  // this block's columns would not fit
+      bwin_flush(part + wc0, win, (int)(cb * 4 - wc0));
+      wc0 = cb * 4;
+    }
     const int64_t u = cb + tc;
     const bool on = u < nu;
     const bool tl = T != 0 && u == U;
@@ -393,10 +417,10 @@ __device__ void phase_p2(const BatchDesc& D, const InstLayout& L, float* s, int 
       const int from = tl ? 4 - T : 0;
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (q >= from) part[e + q] = acc[q];
+        if (q >= from) win[e + q - wc0] = acc[q];
     }
   }
-  __syncthreads();
+  bwin_flush(part + wc0, win, (int)(R - wc0));
 }
 
 __device__ void phase_s1(const BatchDesc& D, const InstLayout& L, float* s, double* sh,
@@ -550,6 +574,7 @@ __global__ __launch_bounds__(kBThreads) void k_batch_run(const BatchDesc* descs,
                                                          BatchHeader* hdr, int64_t slots) {
   __shared__ double sh[kBThreads / kWave];
   __shared__ float lds[4 * kBThreads];
+  __shared__ float win[kBWin];
   __shared__ uint32_t sh_u[2];
   __shared__ Item sh_item;
   __shared__ BatchDesc sh_desc;
@@ -605,14 +630,14 @@ __global__ __launch_bounds__(kBThreads) void k_batch_run(const BatchDesc* descs,
     float* s = (float*)(ws + D.ws_offset);
     hopm_stats* st = stats + it.inst;
     if (it.phase == kP1) {
-      phase_p1(D, L, s, it.tile);
+      phase_p1(D, L, s, it.tile, win);
       if (wg_tile_done(&counters[it.inst], D.nt1, &sh_u[1]))
         wg_push(hdr, items, flags, slots, it.inst, kS1, 1, it.sweep, &sh_u[1]);
     } else if (it.phase == kS1) {
       phase_s1(D, L, s, sh, lds, st);
       wg_push(hdr, items, flags, slots, it.inst, kP2, D.nt2, it.sweep, &sh_u[1]);
     } else if (it.phase == kP2) {
-      phase_p2(D, L, s, it.tile, lds);
+      phase_p2(D, L, s, it.tile, lds, win);
       if (wg_tile_done(&counters[it.inst], D.nt2, &sh_u[1]))
         wg_push(hdr, items, flags, slots, it.inst, kS2, 1, it.sweep, &sh_u[1]);
     } else {
