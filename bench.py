@@ -421,13 +421,14 @@ def run_table1(dev, reps: int = 5):
         for _ in range(2):
             canonical()
         torch.cuda.synchronize()
-        creps = 3
-        e0.record()
-        for _ in range(creps):
+        cts = []
+        for _ in range(5):
+            e0.record()
             canonical()
-        e1.record()
-        torch.cuda.synchronize()
-        cms = e0.elapsed_time(e1) / creps
+            e1.record()
+            torch.cuda.synchronize()
+            cts.append(e0.elapsed_time(e1))
+        cms = statistics.median(cts)
         out[f"{n}^{d}"] = {"tvc_pct_mean": round(statistics.mean(per), 1),
                            "tvc_pct_std": round(statistics.stdev(per), 1) if d > 1 else 0.0,
                            "tvc_pct_per_mode": [round(p, 1) for p in per],
