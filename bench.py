@@ -364,11 +364,26 @@ def run_extras(T, Hs, planted, dev, args):
 TABLE1 = {2: 30623, 3: 979, 4: 175, 5: 63, 6: 31, 7: 19, 8: 13, 9: 10, 10: 8}
 
 
+def median_ms(fn, reps, e0, e1):
+    """Median over reps of one call's time between two events (a single
+    slow call, such as a clock or page-table hiccup, does not move it)."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return statistics.median(ts)
+
+
 def run_table1(dev, reps: int = 5):
     """The paper's Table 1 hypersquare tensors (dims chosen not to be
     multiples of the vector length), here in float32 (same element counts,
     3.3-4.3 GB): %-of-peak of the contraction in every mode and of one HOPM
-    sweep, with mean and unbiased std over the modes (the Table 2 statistic)."""
+    sweep (median of `reps` timed calls each), with mean and unbiased std
+    over the modes (the Table 2 statistic)."""
     import torch
 
     import paper_2501_03121_amd as tvc
@@ -385,23 +400,13 @@ def run_table1(dev, reps: int = 5):
             y = torch.empty(A.numel() // n, dtype=torch.float32, device=dev)
             tvc.contract(A, x, k, out=y)
             torch.cuda.synchronize()
-            e0.record()
-            for _ in range(reps):
-                tvc.contract(A, x, k, out=y)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
+            ms = median_ms(lambda: tvc.contract(A, x, k, out=y), reps, e0, e1)
             per.append(100 * tvc_bytes(dims, k, 4) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
             del y
         x = tvc.pack_vectors(synth.unit_vectors(dims, 60), dev)
         tvc.hopm_iterate(A, x, 1)
         torch.cuda.synchronize()
-        e0.record()
-        for _ in range(reps):
-            tvc.hopm_iterate(A, x, 1)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        ms = median_ms(lambda: tvc.hopm_iterate(A, x, 1), reps, e0, e1)
         sweep = 100 * sweep_bytes(dims, 4) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS
         # The canonical HOPM sweep of Sec. 3 on the same kernels: x_j is the
         # contraction of A with every other vector, one mode at a time (the
@@ -421,14 +426,7 @@ def run_table1(dev, reps: int = 5):
         for _ in range(2):
             canonical()
         torch.cuda.synchronize()
-        cts = []
-        for _ in range(5):
-            e0.record()
-            canonical()
-            e1.record()
-            torch.cuda.synchronize()
-            cts.append(e0.elapsed_time(e1))
-        cms = statistics.median(cts)
+        cms = median_ms(canonical, 5, e0, e1)
         out[f"{n}^{d}"] = {"tvc_pct_mean": round(statistics.mean(per), 1),
                            "tvc_pct_std": round(statistics.stdev(per), 1) if d > 1 else 0.0,
                            "tvc_pct_per_mode": [round(p, 1) for p in per],

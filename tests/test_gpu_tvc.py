@@ -369,3 +369,28 @@ def test_column_strips(dev, fmt):
                 want = float(a @ xs)
                 bound = TOL[fmt] * float(np.abs(a) @ np.abs(xs))
                 assert abs(float(yh[l, j]) - want) <= bound, (fmt, dims, l, j)
+
+
+# Column strips with very short contracted extents: the remainder block of
+# M mod (rows per batch) rows in every strip shape (4 or 8 waves, 1 to 4
+# units per lane), on integer inputs against the plain column kernel and
+# the oracle, bit for bit.
+@pytest.mark.parametrize("M", [1, 2, 3, 5, 7, 9, 31, 33, 37])
+def test_column_strips_short_extents(dev, M):
+    from paper_2501_03121_amd import tune
+    for R in (1 << 16, 5000 * 4 + 1):
+        dims = (64, M, R)
+        base = synth.integers(dims, 60 + M, -8, 8)
+        A = torch.from_numpy(base).float().to(dev)
+        xh = synth.integers(M, 61, -4, 4)
+        x = torch.from_numpy(xh).float().to(dev)
+        p = tvc.contract_plan(A, 1)
+        assert p["family"] == "col" and p["strip_units"] > 0, (dims, p)
+        a = tvc.contract(A, x, 1).clone()
+        tune.set_tuning("col", 0, -1)
+        try:
+            b = tvc.contract(A, x, 1)
+        finally:
+            tune.reset()
+        assert torch.equal(a, b), (dims, p)
+        assert np.array_equal(host(a), O.tvc(base, xh, 1)), (dims, p)
