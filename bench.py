@@ -364,18 +364,20 @@ def run_extras(T, Hs, planted, dev, args):
 TABLE1 = {2: 30623, 3: 979, 4: 175, 5: 63, 6: 31, 7: 19, 8: 13, 9: 10, 10: 8}
 
 
-def median_ms(fn, reps, e0, e1):
-    """Median over reps of one call's time between two events (a single
-    slow call, such as a clock or page-table hiccup, does not move it)."""
+def median_ms(fn, reps, e0=None, e1=None):
+    """Median over reps back-to-back calls of each call's time between two
+    events around it (a single slow call, such as a clock or page-table
+    hiccup, does not move it; the queue stays full, so host launch latency
+    is not counted)."""
     import torch
-    ts = []
-    for _ in range(reps):
-        e0.record()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record()
         fn()
-        e1.record()
-        torch.cuda.synchronize()
-        ts.append(e0.elapsed_time(e1))
-    return statistics.median(ts)
+        b.record()
+    torch.cuda.synchronize()
+    return statistics.median(a.elapsed_time(b) for a, b in ev)
 
 
 def run_table1(dev, reps: int = 5):

@@ -163,8 +163,11 @@ int32_t hopm_iterate(const tvc_tensor* A, double* x, int32_t sweeps, void* ws,
  * max_sweeps sweeps.  Then, if A_refine is not NULL (a TVC_F32 tensor of the
  * same dims, normally the original of a low-precision A), up to
  * refine_sweeps sweeps on A_refine with the same stopping test.  h_out
- * (host) receives the final record.  Returns TVC_OK, TVC_ENOTCONVERGED (the
- * last iterate is still in x), TVC_EDEGENERATE, or an argument error. */
+ * (host) receives the final record; when it is pinned host memory
+ * (hipHostMalloc), each check reads the record back straight into it, which
+ * is faster than the staged copy pageable memory needs.  Returns TVC_OK,
+ * TVC_ENOTCONVERGED (the last iterate is still in x), TVC_EDEGENERATE, or an
+ * argument error. */
 int32_t hopm_solve(const tvc_tensor* A, const tvc_tensor* A_refine, double* x,
                    double tol, int32_t max_sweeps, int32_t check_every,
                    int32_t refine_sweeps, void* ws, size_t ws_bytes,

@@ -7,6 +7,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
+import ctypes
+
 import torch
 
 from . import _lib as L
@@ -196,12 +198,21 @@ def hopm_solve(A: torch.Tensor, x: torch.Tensor, tol: float = 1e-6, max_sweeps: 
     lib = L.lib()
     need = lib.hopm_workspace_bytes(desc)
     ws = _WS.get(need, A.device)
-    h = L.HopmStats()
+    # the result record in pinned host memory: the library reads each
+    # convergence check straight into it
+    global _PINNED_STATS
+    if _PINNED_STATS is None:
+        _PINNED_STATS = torch.empty(ctypes.sizeof(L.HopmStats), dtype=torch.uint8, pin_memory=True)
+    hp = ctypes.cast(_PINNED_STATS.data_ptr(), ctypes.POINTER(L.HopmStats))
     st = lib.hopm_solve(desc, rdesc, x.data_ptr(), float(tol), int(max_sweeps), int(check_every),
-                        int(refine_sweeps), _WS.ptr(ws), int(need), h, _stream())
+                        int(refine_sweeps), _WS.ptr(ws), int(need), hp, _stream())
+    h = L.HopmStats.from_buffer_copy(ctypes.string_at(_PINNED_STATS.data_ptr(), ctypes.sizeof(L.HopmStats)))
     if st not in (L.TVC_OK, L.TVC_ENOTCONVERGED) or (st == L.TVC_ENOTCONVERGED and raise_on_nonconvergence):
         L.check(st)
     return HopmResult(h.lam, h.delta, h.sweeps, h.refine_sweeps, st)
+
+
+_PINNED_STATS = None
 
 
 def quantize(A32: torch.Tensor, fmt: str, truncate: bool = False):

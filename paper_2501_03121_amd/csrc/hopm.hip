@@ -1072,13 +1072,23 @@ int32_t hopm_solve(const tvc_tensor* A, const tvc_tensor* A_refine, double* x, d
   hopm_stats* dst = (hopm_stats*)((char*)ws + Lt.o_stats);
   hipStream_t s = (hipStream_t)stream;
   hopm_stats h{};
+  // The per-check read-back goes straight into h_out when the caller's
+  // record is pinned host memory (a copy to pageable memory is staged and
+  // costs tens of microseconds per check), else into a local record.
+  hopm_stats* rb = &h;
+  {
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, h_out) == hipSuccess && at.type == hipMemoryTypeHost) rb = h_out;
+    (void)hipGetLastError();  // an unregistered pointer reports an error: not ours to keep
+  }
   bool converged = false;
   int done = 0;
   while (done < max_sweeps) {
     const int k = std::min(check_every, max_sweeps - done);
     TVC_TRY(iterate_any(A, x, k, ws, ws_bytes, dst, s));
-    TVC_TRY_HIP(hipMemcpyAsync(&h, dst, sizeof(h), hipMemcpyDeviceToHost, s));
+    TVC_TRY_HIP(hipMemcpyAsync(rb, dst, sizeof(h), hipMemcpyDeviceToHost, s));
     TVC_TRY_HIP(hipStreamSynchronize(s));
+    h = *rb;
     done += k;
     if (h.status != TVC_OK) {
       h.sweeps = done;
@@ -1097,8 +1107,9 @@ int32_t hopm_solve(const tvc_tensor* A, const tvc_tensor* A_refine, double* x, d
     while (rdone < refine_sweeps) {
       const int k = std::min(check_every, refine_sweeps - rdone);
       TVC_TRY(iterate_any(A_refine, x, k, ws, ws_bytes, dst, s));
-      TVC_TRY_HIP(hipMemcpyAsync(&hr, dst, sizeof(hr), hipMemcpyDeviceToHost, s));
+      TVC_TRY_HIP(hipMemcpyAsync(rb, dst, sizeof(hr), hipMemcpyDeviceToHost, s));
       TVC_TRY_HIP(hipStreamSynchronize(s));
+      hr = *rb;
       rdone += k;
       if (hr.status != TVC_OK) {
         h.status = hr.status;
