@@ -50,7 +50,7 @@ __global__ void k_fill(Acc* p, i64 n, Acc v) {
 // are cut into chunks of `chunk` units so that enough waves write at once.
 // Per row one index division; 16-byte nontemporal stores at dword alignment,
 // the ragged end of a row stored element by element.
-template <typename Acc, bool VEC, bool BETA>
+template <typename Acc, bool VEC, bool BETA, bool BLOCKED>
 __global__ __launch_bounds__(kBlock) void k_outer_rows(const Acc* sv, i64 smod, const Acc* v, i64 vdiv,
                                                         Acc* out, i64 rows, i64 n, i64 upr, int tail,
                                                         int glog, i64 chunk, i64 nch, Acc alpha,
@@ -60,12 +60,27 @@ __global__ __launch_bounds__(kBlock) void k_outer_rows(const Acc* sv, i64 smod, 
   const int G = 1 << glog, P = kWave >> glog;
   const int sub = lane & (G - 1), rsub = lane >> glog;
   const i64 nu = upr + (tail > 0 ? 1 : 0);
-  const i64 tasks = (rows + P - 1) / P * nch;
+  // With BLOCKED (rows of several chunks) the task order is (chunk block,
+  // row group, chunk within the block): waves at work together cover a
+  // block of up to 16 chunks of many rows, so a row of v shared by many
+  // rows (mode 0: one row of g for every output row) is read from HBM once
+  // per block and served from the L2 after that.
+  const i64 nrt = (rows + P - 1) / P;
+  const i64 cb = nch < 16 ? nch : 16;
+  const i64 tasks = BLOCKED ? (nch + cb - 1) / cb * nrt * cb : nrt * nch;
   constexpr int wpb = kBlock / kWave;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   for (i64 t = (i64)blockIdx.x * wpb + w; t < tasks; t += (i64)gridDim.x * wpb) {
     i64 rt, ch;
-    divmod(t, nch, rt, ch);
+    if constexpr (BLOCKED) {
+      i64 bq, ci, bb;
+      divmod(t, cb, bq, ci);
+      divmod(bq, nrt, bb, rt);
+      ch = bb * cb + ci;
+      if (ch >= nch) continue;
+    } else {
+      divmod(t, nch, rt, ch);
+    }
     const i64 row = rt * P + rsub;
     if (row >= rows) continue;
     i64 vq, vr, sq, sr;
@@ -338,7 +353,8 @@ int32_t tvc_backward_A(int32_t order, const int64_t* dims, int32_t dtype, int32_
   while (((i64)1 << glog) < nu && glog < 6) ++glog;
   const i64 chunk = nu > kWave ? std::min<i64>(nu, 16 * kWave) : nu;
   const i64 nch = cdiv_(nu, chunk);
-  const i64 tasks = cdiv_(rows, kWave >> glog) * nch;
+  const i64 cbk = std::min<i64>(nch, 16);
+  const i64 tasks = cdiv_(nch, cbk) * cdiv_(rows, kWave >> glog) * cbk;
   const dim3 grd(grid_(cdiv_(tasks, kBlock / kWave))), blk(kBlock);
   const bool b = beta != 0.0;
 #define OUTER(T)                                                                                   \
@@ -346,12 +362,15 @@ int32_t tvc_backward_A(int32_t order, const int64_t* dims, int32_t dtype, int32_
     const T* sp = (const T*)(byrow ? g : x); const T* vp = (const T*)(byrow ? x : g);              \
     const i64 smod = byrow ? L : M, vdiv = byrow ? L : M;                                          \
     T* dp = (T*)dA;                                                                                \
-    if (vec) {                                                                                     \
-      if (b) hipLaunchKernelGGL((k_outer_rows<T, true, true>), grd, blk, 0, st, sp, smod, vp, vdiv, dp, rows, n, upr, tail, glog, chunk, nch, (T)alpha, (T)beta); \
-      else hipLaunchKernelGGL((k_outer_rows<T, true, false>), grd, blk, 0, st, sp, smod, vp, vdiv, dp, rows, n, upr, tail, glog, chunk, nch, (T)alpha, (T)beta); \
+    if (nch > 1) {                                                                                 \
+      if (b) hipLaunchKernelGGL((k_outer_rows<T, true, true, true>), grd, blk, 0, st, sp, smod, vp, vdiv, dp, rows, n, upr, tail, glog, chunk, nch, (T)alpha, (T)beta); \
+      else hipLaunchKernelGGL((k_outer_rows<T, true, false, true>), grd, blk, 0, st, sp, smod, vp, vdiv, dp, rows, n, upr, tail, glog, chunk, nch, (T)alpha, (T)beta); \
+    } else if (vec) {                                                                              \
+      if (b) hipLaunchKernelGGL((k_outer_rows<T, true, true, false>), grd, blk, 0, st, sp, smod, vp, vdiv, dp, rows, n, upr, tail, glog, chunk, nch, (T)alpha, (T)beta); \
+      else hipLaunchKernelGGL((k_outer_rows<T, true, false, false>), grd, blk, 0, st, sp, smod, vp, vdiv, dp, rows, n, upr, tail, glog, chunk, nch, (T)alpha, (T)beta); \
     } else {                                                                                       \
-      if (b) hipLaunchKernelGGL((k_outer_rows<T, false, true>), grd, blk, 0, st, sp, smod, vp, vdiv, dp, rows, n, upr, tail, glog, chunk, nch, (T)alpha, (T)beta); \
-      else hipLaunchKernelGGL((k_outer_rows<T, false, false>), grd, blk, 0, st, sp, smod, vp, vdiv, dp, rows, n, upr, tail, glog, chunk, nch, (T)alpha, (T)beta); \
+      if (b) hipLaunchKernelGGL((k_outer_rows<T, false, true, false>), grd, blk, 0, st, sp, smod, vp, vdiv, dp, rows, n, upr, tail, glog, chunk, nch, (T)alpha, (T)beta); \
+      else hipLaunchKernelGGL((k_outer_rows<T, false, false, false>), grd, blk, 0, st, sp, smod, vp, vdiv, dp, rows, n, upr, tail, glog, chunk, nch, (T)alpha, (T)beta); \
     }                                                                                              \
   } while (0)
   if (dtype == TVC_F64) OUTER(double);
