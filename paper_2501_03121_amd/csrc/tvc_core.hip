@@ -57,7 +57,6 @@ struct ColwShape {
   static constexpr int kThreads = WV * kWave;
   static constexpr int kUnroll = 32 / WV;
 };
-constexpr int kColwMaxThreads = 8 * kWave;
 constexpr int kColwMaxM = 4096;  // weights staged in LDS by the column-strip kernel
 // Short rows with the window: a row-group reduction per row, so more waves
 // per workgroup (1024 threads) to hide its latency, 8 rows per lane per task.
@@ -99,7 +98,8 @@ struct ColArgs {
 // workgroup streams a contiguous stretch of A; otherwise tasks are dealt
 // round-robin over the whole grid.  Measured on gfx950: chunked ranges help
 // the long-row kernel (about 7% on 4 KB rows), round-robin dealing is 3-6%
-// better for the column, slab and short-row kernels.
+// better for the column, slab and short-row kernels; the kernels with the
+// LDS output window need contiguous ranges (block_range below).
 struct TaskRange {
   i64 begin, end, step;
 };
@@ -136,9 +136,11 @@ __device__ __forceinline__ TaskRange block_range(i64 ntasks) {
 // 1 KB stores of each task cut the read rate by a fifth, while the same
 // outputs written in 64-128 KB bursts per workgroup cost about their bytes).
 // A workgroup that produces one contiguous stretch of y in increasing order
-// therefore parks finished outputs in LDS and writes them in bursts: the
-// window holds y[base, base + kWinElems) and is flushed when the next task's
-// outputs would not fit, and at the end.
+// therefore parks finished outputs in LDS and writes them in bursts: window
+// slot i holds y[org + i] (org a 16-byte boundary at or before the first
+// output held), and the window is flushed when the next round of tasks'
+// outputs would not fit, and at the end.  Workgroups that take equal
+// ranges advance in lockstep, so their flushes fall together.
 #ifndef TVC_WIN_BYTES
 #define TVC_WIN_BYTES 131072
 #endif
