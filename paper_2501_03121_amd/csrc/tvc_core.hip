@@ -1274,9 +1274,11 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
         // load need more waves to hide them (32^6 modes 1-3: 54-58 -> 61-66%)
         const int wv = (M < 32 || (win && epv >= 16)) ? 8 : 4;
         // with the window, several units per lane only where rows are a
-        // multiple of 64 KB apart (measured: 32^6 mode 1, 4 MB rows, 75 -> 79%;
-        // 4 KB rows lose 4%)
-        const int cmax = !win ? 4 : ((R * b) % 65536 == 0 ? 4 : 1);
+        // multiple of 64 KB apart and less than 64 MB (measured on 32^6:
+        // float32 mode 1, 4 MB rows, 75 -> 79%, bf16 mode 2, 64 KB rows,
+        // 81 -> 86%; 4 KB rows and 64-128 MB rows lose 2-4%)
+        const i64 pitch = R * b;
+        const int cmax = !win ? 4 : ((pitch % 65536 == 0 && pitch < ((i64)64 << 20)) ? 4 : 1);
         for (int cpt = cmax; cpt >= 1; cpt /= 2) {
           const i64 strips = L * cdiv(nu, (i64)kWave * cpt);
           const bool fits = !win || (i64)wv * kWave * cpt * epv * (i64)ab <= kWinBytes / 2;
