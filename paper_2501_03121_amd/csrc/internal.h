@@ -41,6 +41,7 @@ struct TvcPlan {
   int wv = 4;            // waves per workgroup of the column-strip and windowed slab kernels
   bool strips = false;   // kCol: column strips, a wave per strip (k_colw)
   int cpt = 1;           // kCol strips: column units per lane
+  bool mrot = false;     // kCol strips with the window: workgroup w starts at row w mod M
 };
 
 struct Tuning {

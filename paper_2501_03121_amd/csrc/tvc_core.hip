@@ -90,6 +90,7 @@ struct ColArgs {
   Acc alpha, beta;
   const float* oscale; i64 odiv;
   int tail;  // vector path: columns after the last full unit (< EU)
+  int mrot;  // k_colw with the window: rotate each workgroup's first row
 };
 
 
@@ -513,6 +514,72 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a)
 // the traffic) the strips of a workgroup's contiguous range go to its waves
 // in rounds whose outputs are one stretch of y, collected in the LDS window;
 // without it every output is stored as its strip finishes.
+// All M rows of one strip into acc: batches of RPB rows of CPT units each,
+// the last M mod RPB rows as one more batch.  With ROT the row order starts
+// at row ms and wraps around (row index r + ms, less M past the end): where
+// many slabs' rows are a power-of-two number of MB apart, workgroups that
+// all read the same row index at once load addresses that share their low
+// 20+ bits.  Measured on 32^6 float32 mode 1 (4 MB rows, 128 MB slabs): 75
+// -> 84% of peak.  The same wrapped indexing costs 4-8 points where rows
+// are 4 KB or 64-128 MB apart, with or without a rotation, so it is only
+// compiled into the windowed kernel and taken where the planner asks.
+template <class U, int RPB, int CPT, bool ROT, typename Acc>
+__device__ __forceinline__ void colw_rows(const char* row0, i64 rs, const i64 (&eo)[CPT], const Acc* wl,
+                                          int M, int ms, Acc (&acc)[CPT][U::EU]) {
+  constexpr int EU = U::EU;
+  auto rr = [&](int r) {
+    if constexpr (ROT) {
+      r += ms;
+      return r >= M ? r - M : r;
+    } else {
+      return r;
+    }
+  };
+  int m = 0;
+  for (; m + RPB <= M; m += RPB) {
+    typename U::Raw raw[RPB][CPT];
+#pragma unroll
+    for (int q = 0; q < RPB; ++q)
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) raw[q][j] = U::load(row0 + (i64)rr(m + q) * rs, eo[j]);
+#pragma unroll
+    for (int q = 0; q < RPB; ++q) {
+      const Acc wk = wl[rr(m + q)];
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+        Acc v[EU];
+        U::unpack(raw[q][j], v);
+#pragma unroll
+        for (int e = 0; e < EU; ++e) acc[j][e] = fma(v[e], wk, acc[j][e]);
+      }
+    }
+  }
+  if constexpr (RPB > 1) {
+    if (m < M) {
+      // the last M mod RPB rows, loads issued together (M is uniform)
+      typename U::Raw raw[RPB - 1][CPT];
+#pragma unroll
+      for (int q = 0; q < RPB - 1; ++q)
+#pragma unroll
+        for (int j = 0; j < CPT; ++j)
+          raw[q][j] = m + q < M ? U::load(row0 + (i64)rr(m + q) * rs, eo[j]) : U::zero();
+#pragma unroll
+      for (int q = 0; q < RPB - 1; ++q) {
+        if (m + q < M) {
+          const Acc wk = wl[rr(m + q)];
+#pragma unroll
+          for (int j = 0; j < CPT; ++j) {
+            Acc v[EU];
+            U::unpack(raw[q][j], v);
+#pragma unroll
+            for (int e = 0; e < EU; ++e) acc[j][e] = fma(v[e], wk, acc[j][e]);
+          }
+        }
+      }
+    }
+  }
+}
+
 template <int DT, bool VEC, int ROLE, int WV, int CPT, bool WIN>
 __global__ __launch_bounds__(ColwShape<WV>::kThreads) void k_colw(ColArgs<typename St<DT>::Acc> a) {
   typedef typename St<DT>::Acc Acc;
@@ -575,48 +642,13 @@ __global__ __launch_bounds__(ColwShape<WV>::kThreads) void k_colw(ColArgs<typena
     for (int j = 0; j < CPT; ++j)
 #pragma unroll
       for (int e = 0; e < EU; ++e) acc[j][e] = (Acc)0;
-    int m = 0;
-    for (; m + RPB <= M; m += RPB) {
-      typename U::Raw raw[RPB][CPT];
-#pragma unroll
-      for (int q = 0; q < RPB; ++q)
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) raw[q][j] = U::load(row0 + (i64)(m + q) * rs, eo[j]);
-#pragma unroll
-      for (int q = 0; q < RPB; ++q) {
-        const Acc wk = wl[m + q];
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-          Acc v[EU];
-          U::unpack(raw[q][j], v);
-#pragma unroll
-          for (int e = 0; e < EU; ++e) acc[j][e] = fma(v[e], wk, acc[j][e]);
-        }
-      }
-    }
-    if constexpr (RPB > 1) {
-      if (m < M) {
-        // the last M mod RPB rows, loads issued together (M is uniform)
-        typename U::Raw raw[RPB - 1][CPT];
-#pragma unroll
-        for (int q = 0; q < RPB - 1; ++q)
-#pragma unroll
-          for (int j = 0; j < CPT; ++j)
-            raw[q][j] = m + q < M ? U::load(row0 + (i64)(m + q) * rs, eo[j]) : U::zero();
-#pragma unroll
-        for (int q = 0; q < RPB - 1; ++q) {
-          if (m + q < M) {
-            const Acc wk = wl[m + q];
-#pragma unroll
-            for (int j = 0; j < CPT; ++j) {
-              Acc v[EU];
-              U::unpack(raw[q][j], v);
-#pragma unroll
-              for (int e = 0; e < EU; ++e) acc[j][e] = fma(v[e], wk, acc[j][e]);
-            }
-          }
-        }
-      }
+    // With mrot, workgroup w streams rows w mod M, ..., M - 1, 0, ..., w - 1
+    // (see colw_rows)
+    if constexpr (WIN) {
+      if (a.mrot) colw_rows<U, RPB, CPT, true>(row0, rs, eo, wl, M, (int)(blockIdx.x % (unsigned)M), acc);
+      else colw_rows<U, RPB, CPT, false>(row0, rs, eo, wl, M, 0, acc);
+    } else {
+      colw_rows<U, RPB, CPT, false>(row0, rs, eo, wl, M, 0, acc);
     }
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
@@ -873,7 +905,12 @@ __global__ __launch_bounds__(kRowswThreads) void k_rowsw(RowArgs<typename St<DT>
 // one LDS word holds, so each LDS read feeds VE accumulators (measured:
 // narrow formats lose more to the wider groups' reductions and LDS bank
 // conflicts than they gain, so they read one element at a time).
+// The M weights sit at the end of the staging buffer (the planner keeps the
+// blocks clear of them): read from global memory inside the compute loop,
+// each weight would wait behind the next block's loads, which are issued
+// before the compute and complete in order.
 constexpr int kStageBytes = 32768;
+__host__ __device__ constexpr i64 stage_wres(i64 M, i64 acc_bytes) { return (M * acc_bytes + 15) / 16 * 16; }
 // With the output window: staging buffer, window and threads per workgroup,
 // and workgroups per CU.  The staged kernel needs several blocks in flight
 // per CU more than long bursts: measured on gfx950 over Table 1's staged
@@ -917,6 +954,8 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<typename St<DT>::Acc> a)
   __shared__ uint4 lds[kStageVecs];
   __shared__ __align__(16) Acc win[WIN ? WE : 1];
   const int tid = threadIdx.x;
+  Acc* wl = (Acc*)((char*)lds + kStageVecs * 16 - stage_wres(a.M, sizeof(Acc)));
+  for (i64 i = tid; i < a.M; i += NT) wl[i] = a.w[i];  // visible after the first block's barrier
   const i64 E = a.M * a.R;
   const int G = 1 << a.glog;
   const int sub = tid & (G - 1);
@@ -986,7 +1025,7 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<typename St<DT>::Acc> a)
           } else {
             val[0] = load_elem<DT>(sl, e);
           }
-          const Acc wm = a.w[m];
+          const Acc wm = wl[m];
 #pragma unroll
           for (int v = 0; v < VE; ++v) acc[v] = fma(val[v], wm, acc[v]);
         };
@@ -1156,12 +1195,28 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
                             : (sbytes <= 4096 && nu <= 32 && (p.tail > 0 || !pow2 || nu <= 2));
   if (a16 && small && !tuning().stage_off) {
     const i64 q = 16 / gcd_(16, sbytes);
+    // Slabs per block in a staging buffer of the given size less the
+    // weights.  Where the weights displace slabs from a block whose outputs
+    // were a whole number of 256-byte stretches, keep them so (measured on
+    // 8^10 mode 8, 256-byte slabs: 127 slabs per block, 54%; 120, 66%): the
+    // window's flushes otherwise end inside cache lines.
+    const i64 wres = stage_wres(M, ab);
+    const i64 ob = R * (i64)ab;  // output bytes per slab
+    auto slabs = [&](i64 bytes) {
+      const i64 full = (bytes / sbytes) / q * q;
+      const i64 s = ((bytes - wres) / sbytes) / q * q;
+      if (s == full || full * ob % 256 != 0) return s;
+      const i64 g = 256 / gcd_(256, ob);
+      const i64 q2 = q / gcd_(q, g) * g;
+      const i64 s2 = ((bytes - wres) / sbytes) / q2 * q2;
+      return s2 >= 1 ? s2 : s;
+    };
     // with many blocks, outputs through the LDS window (a block's outputs at
     // most half of it), in blocks of the window variant's staging size
-    const i64 sbw = (kStagewBytes / sbytes) / q * q;
+    const i64 sbw = slabs(kStagewBytes);
     const bool win = kWinOn && !tuning().win_off && sbw >= 1 &&
                      cdiv(L, sbw) >= 4 * (i64)device_cus() && sbw * R * (i64)ab <= kStageWinBytes / 2;
-    const i64 sb = win ? sbw : (kStageBytes / sbytes) / q * q;
+    const i64 sb = win ? sbw : slabs(kStageBytes);
     if (sb >= 1) {
       p.family = kStage;
       p.win = win;
@@ -1288,6 +1343,8 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
             p.win = win;
             p.wv = wv;
             p.cpt = cpt;
+            // rotated row order for rows 1-64 MB apart with 4 units per lane
+            p.mrot = win && cpt == 4 && pitch >= ((i64)1 << 20);
             p.tasks = strips;
             p.grid = grid_for(cdiv(strips, wv), kCol, win ? kWinBlocksPerCu : 4);
             break;
@@ -1402,7 +1459,7 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
     const i64 tc = (p.family == kCol && p.strips) ? (i64)kWave * p.cpt : kBlock / p.splitm;
     const i64 nu = p.upr + (p.tail > 0 ? 1 : 0);
     ColArgs<Acc> a{A, w, y, part, L, M, p.upr, R, (nu + tc - 1) / tc, p.chunk, p.nsplit,
-                   p.glog, (Acc)alpha, (Acc)beta, oscale, odiv, p.tail};
+                   p.glog, (Acc)alpha, (Acc)beta, oscale, odiv, p.tail, p.mrot ? 1 : 0};
     if (p.family == kCol) {
       if (p.strips) {
         launch_colw<DT, ROLE>(p, grd, st, a);

@@ -170,8 +170,12 @@ def _staged_cases(fmt):
     # right extents 12 and 20 are whole 16-byte words in float32 and float64:
     # the staged kernel then reads several columns per LDS word
     words = [((64, 9, 12), 1), ((300, 5, 20), 1)] + ([((500, 6, 32), 1)] if fmt == "e4m3" else [])
+    # a long contracted extent: the weights take up to a quarter of the LDS
+    # staging buffer, which then holds fewer slabs per block
+    big_m = {"f64": 150, "f32": 300, "f16": 600, "bf16": 600, "e4m3": 1300}[fmt]
     return rows + words + [((13,) * 5, 3), ((50, 37, 13), 1), ((1001, 3, 7), 1), ((9, 15, 31), 1),
-                           ((3, 5, 7), 1), ((6, 7, 1, 9), 2), ((2, 3, 4, 5, 6, 7), 4)]
+                           ((3, 5, 7), 1), ((6, 7, 1, 9), 2), ((2, 3, 4, 5, 6, 7), 4),
+                           ((40, big_m, 3), 1)]
 
 
 @pytest.mark.parametrize("fmt", FMTS)
@@ -394,3 +398,34 @@ def test_column_strips_short_extents(dev, M):
             tune.reset()
         assert torch.equal(a, b), (dims, p)
         assert np.array_equal(host(a), O.tvc(base, xh, 1)), (dims, p)
+
+
+# Column strips whose rows are 1 MB apart (4 units per lane, output window):
+# each workgroup starts at its own row and wraps around, including the
+# remainder block of M mod (rows per batch) rows.  On integer inputs the sum
+# is exact in any order, so the result equals the plain column kernel's and
+# the oracle's bit for bit.
+@pytest.mark.parametrize("M", [1, 3, 5, 17])
+def test_column_strips_rotated_rows(dev, M):
+    from paper_2501_03121_amd import tune
+    for fmt, R in (("f32", 1 << 18), ("bf16", 1 << 19)):
+        if fmt == "bf16" and M != 3:
+            continue
+        dims = (32, M, R)
+        base = synth.integers(dims, 70 + M, -8, 8)
+        dt = torch.float32 if fmt == "f32" else torch.bfloat16
+        A = torch.from_numpy(base).to(dt).to(dev)
+        xh = synth.integers(M, 71, -4, 4)
+        x = torch.from_numpy(xh).float().to(dev)
+        p = tvc.contract_plan(A, 1)
+        assert p["family"] == "col" and p["window"] and p["strip_units"] == 4, (fmt, dims, p)
+        assert p["row_rotation"], (fmt, dims, p)
+        a = tvc.contract(A, x, 1).clone()
+        tune.set_tuning("col", 0, -1)
+        try:
+            assert not tvc.contract_plan(A, 1)["row_rotation"]
+            b = tvc.contract(A, x, 1)
+        finally:
+            tune.reset()
+        assert torch.equal(a, b), (fmt, dims)
+        assert np.array_equal(host(a), O.tvc(base, xh, 1)), (fmt, dims)
