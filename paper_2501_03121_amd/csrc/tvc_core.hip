@@ -520,7 +520,7 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a)
 // many slabs' rows are a power-of-two number of MB apart, workgroups that
 // all read the same row index at once load addresses that share their low
 // 20+ bits.  Measured on 32^6 float32 mode 1 (4 MB rows, 128 MB slabs): 75
-// -> 84% of peak.  The same wrapped indexing costs 4-8 points where rows
+// -> 84% of peak.  The same wrapped indexing costs 3-8 points where rows
 // are 4 KB or 64-128 MB apart, with or without a rotation, so it is only
 // compiled into the windowed kernel and taken where the planner asks.
 template <class U, int RPB, int CPT, bool ROT, typename Acc>
@@ -1184,15 +1184,17 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
   // Small slabs: stage whole slabs through LDS where the slab kernel loses
   // coalescing (measured on gfx950 over the Table 1 shapes): slabs of at
   // most 4 KB whose right extent is ragged, not a power of two, or at most
-  // 2 units wide.  Power-of-two slab widths stay with the slab kernel,
-  // which is faster there.  Rows (R == 1) of 33-64 units are staged only in
+  // 2 units wide, or narrower than one 16-byte vector (where a slab lane
+  // would load one element: E4M3 8^10 mode 8, 8-byte rows, 16% of peak).
+  // Other power-of-two slab widths stay with the slab kernel, which is
+  // faster there.  Rows (R == 1) of 33-64 units are staged only in
   // float64, where the row kernel's double accumulators limit occupancy;
   // in the other formats the row kernel is 10-40% faster on them.  A block
   // of sb slabs must be a multiple of 16 bytes.
   const i64 sbytes = M * R * b;
   const bool pow2 = (nu & (nu - 1)) == 0;
   const bool small = R == 1 ? (dtype == TVC_F64 && p.vec && nu > 32 && nu <= 64)
-                            : (sbytes <= 4096 && nu <= 32 && (p.tail > 0 || !pow2 || nu <= 2));
+                            : (sbytes <= 4096 && nu <= 32 && (p.tail > 0 || !pow2 || nu <= 2 || !p.vec));
   if (a16 && small && !tuning().stage_off) {
     const i64 q = 16 / gcd_(16, sbytes);
     // Slabs per block in a staging buffer of the given size less the

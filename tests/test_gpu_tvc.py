@@ -170,6 +170,9 @@ def _staged_cases(fmt):
     # right extents 12 and 20 are whole 16-byte words in float32 and float64:
     # the staged kernel then reads several columns per LDS word
     words = [((64, 9, 12), 1), ((300, 5, 20), 1)] + ([((500, 6, 32), 1)] if fmt == "e4m3" else [])
+    # power-of-two rows narrower than one 16-byte vector (8 and 4 bytes)
+    words += {"e4m3": [((600, 5, 8), 1), ((700, 3, 4), 1)], "bf16": [((600, 5, 4), 1)],
+              "f16": [((600, 5, 4), 1)]}.get(fmt, [])
     # a long contracted extent: the weights take up to a quarter of the LDS
     # staging buffer, which then holds fewer slabs per block
     big_m = {"f64": 150, "f32": 300, "f16": 600, "bf16": 600, "e4m3": 1300}[fmt]
