@@ -514,6 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a)
 // the traffic) the strips of a workgroup's contiguous range go to its waves
 // in rounds whose outputs are one stretch of y, collected in the LDS window;
 // without it every output is stored as its strip finishes.
+
 // All M rows of one strip into acc: batches of RPB rows of CPT units each,
 // the last M mod RPB rows as one more batch.  With ROT the row order starts
 // at row ms and wraps around (row index r + ms, less M past the end): where
