@@ -133,7 +133,9 @@ int32_t tvc_contract(const tvc_tensor* A, int32_t mode, const void* x, void* y,
  * the traffic), [9] family 1: column units per lane of the column-strip
  * kernel (a wave per strip of 64 times that many units), 0 for wave groups
  * sharing column tiles, [10] 1 if the column-strip kernel's workgroups
- * start their rows at different row indices (rows 1-64 MB apart).
+ * start their rows at different row indices (rows 1-64 MB apart), [11]
+ * family 3: slabs per block copied through the 32 KB LDS staging buffer
+ * (the block and the M weights share it), 0 otherwise.
  * Returns TVC_OK or an argument error. */
 int32_t tvc_contract_plan(const tvc_tensor* A, int32_t mode, int32_t* info, int32_t n);
 

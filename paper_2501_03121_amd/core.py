@@ -123,12 +123,12 @@ def contract_plan(A: torch.Tensor, mode: int, scale: torch.Tensor | None = None)
     """Which kernel tvc_contract(A, mode) launches, and with what shape."""
     import ctypes
     desc = describe(A, scale)
-    info = (ctypes.c_int32 * 11)()
-    L.check(L.lib().tvc_contract_plan(desc, mode, info, 11))
+    info = (ctypes.c_int32 * 12)()
+    L.check(L.lib().tvc_contract_plan(desc, mode, info, 12))
     return {"family": _FAMILY[info[0]], "vec": bool(info[1]), "split_m": info[2],
             "nsplit": info[3], "grid": info[4], "lanes_per_row": info[5], "tail": info[6],
             "units_per_row": info[7], "window": bool(info[8]), "strip_units": info[9],
-            "row_rotation": bool(info[10])}
+            "row_rotation": bool(info[10]), "stage_slabs": info[11]}
 
 
 @dataclass

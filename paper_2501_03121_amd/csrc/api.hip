@@ -229,11 +229,12 @@ int32_t tvc_contract_plan(const tvc_tensor* A, int32_t mode, int32_t* info, int3
   const bool a4 = ((uintptr_t)A->data % 4) == 0;
   const bool a16 = ((uintptr_t)A->data % 16) == 0;
   TvcPlan p = plan_tvc(A->dtype, L, M, R, a4, true, a16);
-  const int32_t v[11] = {p.family, p.vec ? 1 : 0, p.splitm, p.nsplit, p.grid,
+  const int32_t v[12] = {p.family, p.vec ? 1 : 0, p.splitm, p.nsplit, p.grid,
                          (p.family == kCol || (p.family == kRow && p.lng)) ? 0 : (1 << p.glog),
                          p.tail, (int32_t)std::min<i64>(p.upr, INT32_MAX), p.win ? 1 : 0,
-                         (p.family == kCol && p.strips) ? p.cpt : 0, p.mrot ? 1 : 0};
-  for (int i = 0; i < n && i < 11; ++i) info[i] = v[i];
+                         (p.family == kCol && p.strips) ? p.cpt : 0, p.mrot ? 1 : 0,
+                         p.family == kStage ? (int32_t)p.sb : 0};
+  for (int i = 0; i < n && i < 12; ++i) info[i] = v[i];
   return TVC_OK;
 }
 

@@ -144,3 +144,42 @@ def test_batch_and_tuning_argument_errors():
     assert lib.tvc_contract_plan(t, 2, info, 9) == L.TVC_OK and info[8] == 1
     t = tensor((64, 1024, 1024), dtype=L.TVC_F32)        # long columns: direct stores
     assert lib.tvc_contract_plan(t, 1, info, 9) == L.TVC_OK and info[0] == 1 and info[8] == 0
+
+
+# The staged kernel copies blocks of whole slabs into a 32 KB LDS buffer
+# whose end holds the M weights (accumulator type, 16-byte aligned), and
+# loads a block with 16-byte vectors; with the output window (8 KB) a
+# block's outputs take at most half of it.  The planner's block sizes must
+# keep all of that in bounds, for every format and many slab shapes.
+def test_staged_blocks_fit_their_lds():
+    import itertools
+    eb = {L.TVC_F64: 8, L.TVC_F32: 4, L.TVC_F16: 2, L.TVC_BF16: 2, L.TVC_F8E4M3: 1}
+    ab = {L.TVC_F64: 8, L.TVC_F32: 4, L.TVC_F16: 4, L.TVC_BF16: 4, L.TVC_F8E4M3: 4}
+    shapes = [(n,) * d for n, d in ((31, 6), (19, 7), (13, 8), (10, 9), (8, 10))]
+    shapes += [(40, m, r) for m, r in itertools.product((1, 3, 8, 37, 150, 300, 600, 1300, 2000),
+                                                       (1, 2, 3, 4, 5, 7, 8, 12, 13, 20, 31, 32))]
+    shapes += [(300000, 9, 13), (64, 9, 12), (3000, 91, 1), (600, 5, 8), (700, 3, 4)]
+    seen = 0
+    for dims in shapes:
+        for dt in eb:
+            scale = (1 << 21) if dt == L.TVC_F8E4M3 else None
+            t = tensor(dims, dtype=dt, data=1 << 20, scale=scale)
+            for k in range(len(dims)):
+                info = (ctypes.c_int32 * 12)()
+                assert L.lib().tvc_contract_plan(t, k, info, 12) == L.TVC_OK
+                if info[0] != 3:
+                    assert info[11] == 0
+                    continue
+                seen += 1
+                M = dims[k]
+                R = 1
+                for n in dims[k + 1:]:
+                    R *= n
+                sb = info[11]
+                block = sb * M * R * eb[dt]
+                wres = (M * ab[dt] + 15) // 16 * 16
+                assert sb >= 1 and block % 16 == 0, (dims, dt, k, sb)
+                assert block + wres <= 32768, (dims, dt, k, sb, block, wres)
+                if info[8]:
+                    assert sb * R * ab[dt] <= 4096, (dims, dt, k, sb)
+    assert seen > 100
