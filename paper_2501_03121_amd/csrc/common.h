@@ -72,6 +72,13 @@ template <> __device__ __forceinline__ void unpack16<TVC_F8E4M3>(const uint4& r,
   e4m3x4(r.x, o); e4m3x4(r.y, o + 4); e4m3x4(r.z, o + 8); e4m3x4(r.w, o + 12);
 }
 
+// One dword of a narrow format, promoted: 2 fp16 / bf16 or 4 E4M3 values
+// (low bits first).
+template <int DT> __device__ __forceinline__ void unpack4(uint32_t w, float* o);
+template <> __device__ __forceinline__ void unpack4<TVC_BF16>(uint32_t w, float* o) { o[0] = bf16_lo(w); o[1] = bf16_hi(w); }
+template <> __device__ __forceinline__ void unpack4<TVC_F16>(uint32_t w, float* o) { o[0] = f16_bits(w); o[1] = f16_bits(w >> 16); }
+template <> __device__ __forceinline__ void unpack4<TVC_F8E4M3>(uint32_t w, float* o) { e4m3x4(w, o); }
+
 // 16-byte vectors that need only dword alignment.  Multi-dword global
 // accesses on CDNA need a dword-aligned address, not a 16-byte-aligned one,
 // so rows whose length is not a whole number of 16-byte vectors (odd

@@ -903,9 +903,11 @@ __global__ __launch_bounds__(kRowswThreads) void k_rowsw(RowArgs<typename St<DT>
 // per output group split the contracted extent and combine with shuffles.
 // For 4- and 8-byte elements, when a slab row is a whole number of 16-byte
 // words, an output group is the VE = 16 / element-size consecutive columns
-// one LDS word holds, so each LDS read feeds VE accumulators (measured:
-// narrow formats lose more to the wider groups' reductions and LDS bank
-// conflicts than they gain, so they read one element at a time).
+// one LDS word holds, so each LDS read feeds VE accumulators.  Narrow
+// formats read one dword (2 fp16 / bf16 or 4 E4M3 columns) when a slab row
+// is a whole number of dwords, else one element: 16-byte words lost more
+// to the wider groups' reductions and LDS bank conflicts than they gained
+// (E4M3 32^6 mode 4: 37 -> 26% of peak), dwords gain (39 -> 53%).
 // The M weights sit at the end of the staging buffer (the planner keeps the
 // blocks clear of them): read from global memory inside the compute loop,
 // each weight would wait behind the next block's loads, which are issued
@@ -1023,6 +1025,8 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<typename St<DT>::Acc> a)
           Acc val[VE];
           if constexpr (VB == 16) {
             unpack16<DT>(*(const uint4*)(sl + e), val);
+          } else if constexpr (VB == 4) {
+            unpack4<DT>(*(const uint32_t*)(sl + e), val);
           } else {
             val[0] = load_elem<DT>(sl, e);
           }
@@ -1226,8 +1230,9 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
       p.sb = sb;
       p.vec = true;
       // LDS word per read: 16 bytes for 4- and 8-byte elements when a slab
-      // row is a whole number of them, else one element
-      p.stage_vb = (b >= 4 && (R * b) % 16 == 0) ? 16 : 0;
+      // row is a whole number of them, a dword for narrower ones when a row
+      // is a whole number of dwords, else one element
+      p.stage_vb = (b >= 4 && (R * b) % 16 == 0) ? 16 : (b < 4 && (R * b) % 4 == 0) ? 4 : 0;
       const i64 ve = p.stage_vb == 0 ? 1 : p.stage_vb / b;
       p.nsplit = 1;
       p.tasks = cdiv(L, sb);
@@ -1422,14 +1427,14 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
   const dim3 grd(p.grid);
   if (p.family == kStage) {
     StageArgs<Acc> a{A, w, y, L, M, R, p.sb, p.tasks, p.glog, (Acc)alpha, (Acc)beta, oscale, odiv};
-    constexpr int VW = (DT == TVC_F32 || DT == TVC_F64) ? 16 : 0;
+    constexpr int VW = (DT == TVC_F32 || DT == TVC_F64) ? 16 : 4;
     if (p.win) {
       const dim3 wblk(kStagewThreads);
-      if (p.stage_vb == 16 && VW == 16)
+      if (p.stage_vb != 0 && p.stage_vb == VW)
         hipLaunchKernelGGL((k_stage<DT, ROLE, VW, kStagewThreads, true>), grd, wblk, 0, st, a);
       else hipLaunchKernelGGL((k_stage<DT, ROLE, 0, kStagewThreads, true>), grd, wblk, 0, st, a);
     } else {
-      if (p.stage_vb == 16 && VW == 16)
+      if (p.stage_vb != 0 && p.stage_vb == VW)
         hipLaunchKernelGGL((k_stage<DT, ROLE, VW, kBlock, false>), grd, blk, 0, st, a);
       else hipLaunchKernelGGL((k_stage<DT, ROLE, 0, kBlock, false>), grd, blk, 0, st, a);
     }
