@@ -537,6 +537,53 @@ __device__ __forceinline__ void colw_rows(const char* row0, i64 rs, const i64 (&
     }
   };
   int m = 0;
+  // E4M3 spends 24 vector instructions on each 16-byte load, so a wave
+  // would sit on its arithmetic with no loads in flight: there the next
+  // batch's loads are issued before the current batch is summed (same
+  // order of sums).
+  if constexpr (!ROT && EU >= 16) {
+    if (M >= RPB) {
+      typename U::Raw cur[RPB][CPT];
+#pragma unroll
+      for (int q = 0; q < RPB; ++q)
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) cur[q][j] = U::load(row0 + (i64)q * rs, eo[j]);
+      for (; m + 2 * RPB <= M; m += RPB) {
+        typename U::Raw nxt[RPB][CPT];
+#pragma unroll
+        for (int q = 0; q < RPB; ++q)
+#pragma unroll
+          for (int j = 0; j < CPT; ++j) nxt[q][j] = U::load(row0 + (i64)(m + RPB + q) * rs, eo[j]);
+#pragma unroll
+        for (int q = 0; q < RPB; ++q) {
+          const Acc wk = wl[m + q];
+#pragma unroll
+          for (int j = 0; j < CPT; ++j) {
+            Acc v[EU];
+            U::unpack(cur[q][j], v);
+#pragma unroll
+            for (int e = 0; e < EU; ++e) acc[j][e] = fma(v[e], wk, acc[j][e]);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < RPB; ++q)
+#pragma unroll
+          for (int j = 0; j < CPT; ++j) cur[q][j] = nxt[q][j];
+      }
+#pragma unroll
+      for (int q = 0; q < RPB; ++q) {
+        const Acc wk = wl[m + q];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+          Acc v[EU];
+          U::unpack(cur[q][j], v);
+#pragma unroll
+          for (int e = 0; e < EU; ++e) acc[j][e] = fma(v[e], wk, acc[j][e]);
+        }
+      }
+      m += RPB;
+    }
+  }
   for (; m + RPB <= M; m += RPB) {
     typename U::Raw raw[RPB][CPT];
 #pragma unroll
