@@ -901,6 +901,20 @@ __global__ __launch_bounds__(kRowswThreads) void k_rowsw(RowArgs<typename St<DT>
   }
   const i64 per = (i64)P * UN;
   const TaskRange tr = block_range((a.L + per - 1) / per);
+  auto load_task = [&](i64 t, typename U::Raw (&r)[UN]) {
+#pragma unroll
+    for (int k = 0; k < UN; ++k) {
+      const i64 row = t * per + (i64)k * P + rsub;
+      r[k] = (active && row < a.L) ? U::load(a.A, row * a.ld + eo) : U::zero();
+    }
+  };
+  // E4M3 spends 24 vector instructions on each 16-byte load: a wave loads
+  // its next round's rows before summing this round's (same sums)
+  constexpr bool PIPE = EU >= 16;
+  typename U::Raw nxt[PIPE ? UN : 1];
+  if constexpr (PIPE) {
+    if (tr.begin + wv < tr.end) load_task(tr.begin + wv, nxt);
+  }
   i64 org = 0, wbase = 0, wend = 0;
   for (i64 t0 = tr.begin; t0 < tr.end; t0 += WPB) {
     const i64 tlast = min(t0 + WPB, tr.end) - 1;
@@ -916,14 +930,18 @@ __global__ __launch_bounds__(kRowswThreads) void k_rowsw(RowArgs<typename St<DT>
     }
     wend = ye;
     const i64 t = t0 + wv;
-    if (t > tlast) continue;
-    const i64 base = t * per;
     typename U::Raw raw[UN];
+    if constexpr (PIPE) {
+      // this round's rows were loaded in the last round; load the next's
 #pragma unroll
-    for (int k = 0; k < UN; ++k) {
-      const i64 row = base + (i64)k * P + rsub;
-      raw[k] = (active && row < a.L) ? U::load(a.A, row * a.ld + eo) : U::zero();
+      for (int k = 0; k < UN; ++k) raw[k] = nxt[k];
+      if (t + WPB < tr.end) load_task(t + WPB, nxt);
+      if (t > tlast) continue;
+    } else {
+      if (t > tlast) continue;
+      load_task(t, raw);
     }
+    const i64 base = t * per;
 #pragma unroll
     for (int k = 0; k < UN; ++k) {
       Acc v[EU];
