@@ -1442,7 +1442,9 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
       p.grid = grid_for(cdiv(p.tasks, waves_per_block), kSlab, 4);
       if (p.nsplit == 1 && win_ok(M, groups)) {
         p.win = true;
-        p.wv = M < 32 ? 8 : 4;
+        // 8 waves for short slabs and for the 2- and 1-byte formats, whose
+        // slab rows are narrower (32^6 bf16 mode 4: 76 -> 77.5%)
+        p.wv = (M < 32 || b < 4) ? 8 : 4;
         p.grid = grid_for(cdiv(p.tasks, p.wv), kSlab, kWinBlocksPerCu);
       }
     }
