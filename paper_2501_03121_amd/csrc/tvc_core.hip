@@ -263,6 +263,76 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
     }
   }
   const TaskRange tr = wave_tasks<true>(ntasks);
+  // E4M3 rows that are one pass of the wave (weights in registers, no
+  // ragged end): each 16-byte load costs 24 vector instructions, so a wave
+  // loads its next row group before summing the current one (same sums).
+  if constexpr (EU >= 16 && ROLE != kRoleRowWeights) {
+    if (wreg && a.tail == 0) {
+      auto load_group = [&](i64 g, typename U::Raw (&raw)[KU][RB]) {
+#pragma unroll
+        for (int k = 0; k < KU; ++k) {
+          const i64 uk = lane + (i64)k * kWave;
+          const bool ok = uk < a.upr;
+#pragma unroll
+          for (int r = 0; r < RB; ++r) {
+            const i64 row = g * RB + r;
+            raw[k][r] = (ok && row < a.L) ? U::load(a.A, row * a.ld + uk * EU) : U::zero();
+          }
+        }
+      };
+      typename U::Raw nxt[KU][RB];
+      if (tr.begin < tr.end) load_group(tr.begin, nxt);
+      for (i64 t = tr.begin; t < tr.end; t += tr.step) {
+        typename U::Raw raw[KU][RB];
+#pragma unroll
+        for (int k = 0; k < KU; ++k)
+#pragma unroll
+          for (int r = 0; r < RB; ++r) raw[k][r] = nxt[k][r];
+        if (t + tr.step < tr.end) load_group(t + tr.step, nxt);
+        Acc acc[RB][NA];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int e = 0; e < NA; ++e) acc[r][e] = (Acc)0;
+#pragma unroll
+        for (int k = 0; k < KU; ++k)
+#pragma unroll
+          for (int r = 0; r < RB; ++r) {
+            Acc v[EU];
+            U::unpack(raw[k][r], v);
+#pragma unroll
+            for (int e = 0; e < EU; ++e) acc[r][e % NA] = fma(v[e], wv[k][e], acc[r][e % NA]);
+          }
+        // the butterfly reduction and store of the general path below
+        Acc v[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          v[r] = (Acc)0;
+#pragma unroll
+          for (int e = 0; e < NA; ++e) v[r] += acc[r][e];
+        }
+        int rsel = 0;
+#pragma unroll
+        for (int h = RB / 2, off = kWave / 2; h >= 1; h /= 2, off /= 2) {
+          const bool up = (lane & off) != 0;
+#pragma unroll
+          for (int i = 0; i < h; ++i) {
+            const Acc keep = up ? v[i + h] : v[i];
+            const Acc send = up ? v[i] : v[i + h];
+            v[i] = keep + shfl_xor(send, off);
+          }
+          rsel += up ? h : 0;
+        }
+        Acc s_ = v[0];
+#pragma unroll
+        for (int off = kWave / (2 * RB); off >= 1; off /= 2) s_ += shfl_xor(s_, off);
+        const i64 row = t * RB + rsel;
+        if ((lane & (kWave / RB - 1)) == 0 && row < a.L)
+          a.y[row] = epilogue(s_, a.y, row, row, a.alpha, a.beta, a.oscale, a.odiv);
+      }
+      return;
+    }
+  }
   for (i64 t = tr.begin; t < tr.end; t += tr.step) {
     i64 s, g;
     divmod(t, ngroups, s, g);

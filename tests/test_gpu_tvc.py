@@ -432,3 +432,21 @@ def test_column_strips_rotated_rows(dev, M):
             tune.reset()
         assert torch.equal(a, b), (fmt, dims)
         assert np.array_equal(host(a), O.tvc(base, xh, 1)), (fmt, dims)
+
+
+# E4M3 rows that are one pass of a wave (1024 and 3072 bytes: 8 and 2 rows
+# per wave) take a path that loads the next row group before summing the
+# current one; odd row counts end inside a group.  Parity with the oracle,
+# with an alpha/beta epilogue.
+def test_e4m3_one_pass_rows(dev):
+    for dims in ((301, 1024), (37, 3072), (5, 7, 1024)):
+        k = len(dims) - 1
+        A, S, exact = stored_tensor(dims, "e4m3", 80, dev)
+        p = tvc.contract_plan(A, k, scale=S)
+        assert p["family"] == "row" and p["nsplit"] == 1 and p["tail"] == 0, (dims, p)
+        x, xh = vec(dims[k], 81, "e4m3", dev)
+        y0 = synth.uniform(O.output_dims(dims, k), 82)
+        out = torch.from_numpy(y0).float().to(dev)
+        tvc.contract(A, x, k, alpha=0.75, beta=-0.5, out=out, scale=S)
+        ref = O.tvc(exact, xh, k, alpha=0.75, beta=-0.5, y=y0)
+        assert O.rel_err(host(out), ref) <= TOL["e4m3"], dims
