@@ -15,6 +15,11 @@ names the singular value):
   * delta = max_j ||x_j(sweep i) - x_j(sweep i-1)||_2, tested after a sweep.
   * a zero-norm contraction result is an error (the vector cannot be scaled).
 
+`leave_one_out_kron` gives the same vector as the multilinear form
+sum_{l,r} A[l,m,r] wl[l] wr[r] on the (u, n_j, v) view with Kronecker weight
+vectors (two matrix-vector products, blocked for tensors too large to upcast
+whole); `hopm(..., form="kron")` uses it for tensors of 10^9 elements and more.
+
 `dhopm3` follows Algorithm 1 (dHOPM_3) at one process: three buffers, with the
 buffer W carried from j to j+1 for j >= 1.  It is a schedule model, used to
 check the contraction count (d-1)(d+2)/2 per sweep and that it reaches the
@@ -27,7 +32,7 @@ from typing import Sequence
 
 import numpy as np
 
-from .tvc import tvc
+from .tvc import matricized_dims, tvc
 
 
 class DegenerateError(ValueError):
@@ -66,6 +71,62 @@ def leave_one_out(A64: np.ndarray, xs: Sequence[np.ndarray], j: int,
     return np.asarray(Y, dtype=np.float64).reshape(-1)
 
 
+def kron(vecs: Sequence[np.ndarray]) -> np.ndarray:
+    """v_0 (x) v_1 (x) ... as one flat float64 vector, the last vector varying
+    fastest (the last-order layout of Sec. 3); [1.0] for an empty list."""
+    out = np.ones(1)
+    for v in vecs:
+        out = np.multiply.outer(out, np.asarray(v, dtype=np.float64).reshape(-1)).reshape(-1)
+    return out
+
+
+def leave_one_out_kron(A: np.ndarray, xs: Sequence[np.ndarray], j: int,
+                       block_elems: int = 1 << 26, workers: int = 1) -> np.ndarray:
+    """The vector of `leave_one_out`, written as the multilinear form on the
+    (u, n_j, v) view of Sec. 3:
+        y[m] = sum_{l, r} A[l, m, r] * wl[l] * wr[r],
+        wl = x_0 (x) ... (x) x_{j-1},   wr = x_{j+1} (x) ... (x) x_{d-1}.
+    Two library matrix-vector products: the larger of l and r is contracted
+    first.  For tensors too large to upcast whole, the first product runs
+    over blocks of about `block_elems` elements (each block upcast exactly to
+    float64 on its own) and the block results are added in block order;
+    `workers` threads may compute the blocks (the order of the additions does
+    not change).  A may be float32; every product is float64.
+    """
+    A = np.asarray(A)
+    d = A.ndim
+    u, n, v = matricized_dims(A.shape, j)
+    wl = kron(xs[:j])
+    wr = kron(xs[j + 1:])
+    if v >= u:
+        # z[l, m] = sum_r A[l, m, r] wr[r], over blocks of (l, m) rows
+        A2 = A.reshape(u * n, v)
+        rows = max(1, block_elems // v)
+        starts = range(0, u * n, rows)
+        parts = _map(lambda p0: np.asarray(A2[p0:p0 + rows], dtype=np.float64) @ wr, starts, workers)
+        z = np.concatenate(parts)
+        return wl @ z.reshape(u, n)
+    # z[m, r] = sum_l wl[l] A[l, m, r], over blocks of l
+    A2 = A.reshape(u, n * v)
+    rows = max(1, block_elems // (n * v))
+    starts = range(0, u, rows)
+    parts = _map(lambda l0: wl[l0:l0 + rows] @ np.asarray(A2[l0:l0 + rows], dtype=np.float64),
+                 starts, workers)
+    z = np.zeros(n * v, dtype=np.float64)
+    for p in parts:
+        z += p
+    return z.reshape(n, v) @ wr
+
+
+def _map(fn, items, workers: int) -> list:
+    """[fn(i) for i in items], on `workers` threads when workers > 1."""
+    if workers <= 1:
+        return [fn(i) for i in items]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, items))
+
+
 def _touched(log: list, nvec: int) -> int:
     # Eq. (3) accounting: every contraction reads its input tensor and its
     # vector and writes its output; the normalisation touches 3 n elements.
@@ -73,12 +134,19 @@ def _touched(log: list, nvec: int) -> int:
 
 
 def hopm(A: np.ndarray, xs0: Sequence[np.ndarray], sweeps: int | None = None,
-         tol: float | None = None, max_sweeps: int = 1000) -> HopmResult:
+         tol: float | None = None, max_sweeps: int = 1000, form: str = "chain",
+         workers: int = 1) -> HopmResult:
     """Canonical Gauss-Seidel HOPM in float64.
 
     Runs `sweeps` sweeps, or, if `sweeps` is None, until delta < tol or
-    `max_sweeps` sweeps.
+    `max_sweeps` sweeps.  form = "chain" forms each leave-one-out vector by
+    d - 1 contractions (`leave_one_out`); form = "kron" by the multilinear
+    form of `leave_one_out_kron` (the same vector, for tensors whose chain of
+    contractions would be slow on the host; A is then upcast block by block
+    on `workers` threads and may stay float32).
     """
+    if form == "kron":
+        return _hopm_kron(A, xs0, sweeps, tol, max_sweeps, workers)
     A64 = np.asarray(A, dtype=np.float64)
     d = A64.ndim
     if d < 2:
@@ -101,6 +169,36 @@ def hopm(A: np.ndarray, xs0: Sequence[np.ndarray], sweeps: int | None = None,
             res.norms.append(nrm)
             res.tvcs += len(log)
             res.touched += _touched(log, A64.shape[j])
+        res.lam = res.norms[-1]
+        res.sweeps += 1
+        delta = max(float(np.linalg.norm(xs[j] - old[j])) for j in range(d))
+        res.deltas.append(delta)
+        res.lams.append(res.lam)
+        if sweeps is None and tol is not None and delta < tol:
+            break
+    res.xs = xs
+    return res
+
+
+def _hopm_kron(A: np.ndarray, xs0: Sequence[np.ndarray], sweeps: int | None,
+               tol: float | None, max_sweeps: int, workers: int = 1) -> HopmResult:
+    """`hopm` with each leave-one-out vector from `leave_one_out_kron`."""
+    A = np.asarray(A)
+    d = A.ndim
+    if d < 2:
+        raise ValueError("HOPM needs order >= 2")
+    xs = [np.asarray(x, dtype=np.float64).reshape(-1).copy() for x in xs0]
+    res = HopmResult(xs=xs, lam=0.0, sweeps=0)
+    limit = sweeps if sweeps is not None else max_sweeps
+    for _ in range(limit):
+        old = [x.copy() for x in xs]
+        for j in range(d):
+            y = leave_one_out_kron(A, xs, j, workers=workers)
+            nrm = float(np.linalg.norm(y))
+            if nrm == 0.0:
+                raise DegenerateError(f"zero-norm contraction at j={j}")
+            xs[j] = y / nrm
+            res.norms.append(nrm)
         res.lam = res.norms[-1]
         res.sweeps += 1
         delta = max(float(np.linalg.norm(xs[j] - old[j])) for j in range(d))

@@ -114,3 +114,68 @@ def test_lambda_is_full_contraction():
     A = synth.normal(dims, 31)
     r = H.hopm(A, synth.unit_vectors(dims, 32), sweeps=3)
     assert abs(O.contract_all(A, r.xs, range(3)) - r.lam) < 1e-12 * r.lam
+
+
+def _loo_brute(A, xs, j):
+    # every multi-index of A, one product per element (tiny tensors only)
+    import itertools
+    y = np.zeros(A.shape[j])
+    for idx in itertools.product(*[range(n) for n in A.shape]):
+        p = float(A[idx])
+        for i, x in enumerate(xs):
+            if i != j:
+                p *= float(x[idx[i]])
+        y[idx[j]] += p
+    return y
+
+
+@pytest.mark.parametrize("dims", [(7, 5), (3, 4, 5), (2, 3, 4, 3), (3, 2, 2, 3, 2)])
+@pytest.mark.parametrize("block,workers", [(1 << 26, 1), (7, 1), (1, 1), (7, 3)])
+def test_kron_leave_one_out_brute_force(dims, block, workers):
+    A = synth.normal(dims, 21)
+    xs = [synth.uniform(n, 22 + i) for i, n in enumerate(dims)]
+    for j in range(len(dims)):
+        ref = _loo_brute(A, xs, j)
+        got = H.leave_one_out_kron(A, xs, j, block_elems=block, workers=workers)
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12)
+        if workers > 1:
+            # threads change nothing: the block results are added in order
+            np.testing.assert_array_equal(got, H.leave_one_out_kron(A, xs, j, block_elems=block))
+        np.testing.assert_allclose(H.leave_one_out(A, xs, j), ref, rtol=1e-12, atol=1e-12)
+
+
+def test_kron_leave_one_out_rank1_closed_form():
+    dims = (4, 6, 5, 3)
+    a = synth.unit_vectors(dims, 31)
+    T = np.ones(())
+    for v in a:
+        T = np.multiply.outer(T, v)
+    xs = [synth.uniform(n, 32 + i) for i, n in enumerate(dims)]
+    for j in range(4):
+        c = 2.5 * np.prod([np.dot(a[i], xs[i]) for i in range(4) if i != j])
+        np.testing.assert_allclose(H.leave_one_out_kron(2.5 * T, xs, j, block_elems=5), c * a[j],
+                                   rtol=1e-12, atol=1e-14)
+
+
+def test_kron_order_of_kronecker_vector():
+    # last vector fastest: (a (x) b)[i * len(b) + k] = a[i] b[k]
+    a, b = np.array([1.0, 2.0]), np.array([3.0, 5.0, 7.0])
+    np.testing.assert_array_equal(H.kron([a, b]), [3, 5, 7, 6, 10, 14])
+    np.testing.assert_array_equal(H.kron([]), [1.0])
+
+
+@pytest.mark.parametrize("dims", [(9, 7, 8), (3, 4, 2, 3, 5, 2, 3), (2, 3, 2, 3, 2, 2, 3, 2, 2)])
+def test_kron_form_hopm_equals_chain(dims):
+    A = synth.normal(dims, 41)
+    x0 = synth.unit_vectors(dims, 42)
+    c = H.hopm(A, x0, sweeps=5)
+    k = H.hopm(A, x0, sweeps=5, form="kron")
+    np.testing.assert_allclose(k.norms, c.norms, rtol=1e-12)
+    np.testing.assert_allclose(k.deltas, c.deltas, rtol=1e-9, atol=1e-14)
+    for u, v in zip(k.xs, c.xs):
+        np.testing.assert_allclose(u, v, rtol=1e-11, atol=1e-12)
+    # a float32 input is upcast exactly: same as passing its float64 copy
+    A32 = A.astype(np.float32)
+    k32 = H.hopm(A32, x0, sweeps=2, form="kron")
+    k64 = H.hopm(A32.astype(np.float64), x0, sweeps=2, form="kron")
+    np.testing.assert_array_equal(k32.norms, k64.norms)
