@@ -50,7 +50,7 @@ typedef enum {
   TVC_EWORKSPACE = 4,    /* workspace NULL, misaligned or too small */
   TVC_EHIP = 5,          /* a HIP runtime call or kernel launch failed */
   TVC_EDEGENERATE = 6,   /* a vector to normalise had zero norm */
-  TVC_ENOTCONVERGED = 7  /* max_sweeps reached before delta < tol */
+  TVC_ENOTCONVERGED = 7  /* a sweep cap reached before delta < tol */
 } tvc_status;
 
 typedef enum {
@@ -164,12 +164,16 @@ int32_t hopm_iterate(const tvc_tensor* A, double* x, int32_t sweeps, void* ws,
 /* Sweeps on A until delta < tol (tested every `check_every` sweeps, which
  * reads the stats back to the host and synchronises the stream) or
  * max_sweeps sweeps.  Then, if A_refine is not NULL (a TVC_F32 tensor of the
- * same dims, normally the original of a low-precision A), up to
- * refine_sweeps sweeps on A_refine with the same stopping test.  h_out
- * (host) receives the final record; when it is pinned host memory
- * (hipHostMalloc), each check reads the record back straight into it, which
- * is faster than the staged copy pageable memory needs.  Returns TVC_OK,
- * TVC_ENOTCONVERGED (the last iterate is still in x), TVC_EDEGENERATE, or an
+ * same dims, normally the original of a low-precision A) and refine_sweeps
+ * > 0, a refinement stage: up to refine_sweeps sweeps on A_refine with the
+ * same stopping test, whether or not the first stage met tol.  h_out (host)
+ * receives the final record: sweeps of the first stage, refine_sweeps of the
+ * refinement, lambda and delta of the last sweep run.  When h_out is pinned
+ * host memory (hipHostMalloc), each check reads the record back straight
+ * into it, which is faster than the staged copy pageable memory needs.
+ * Returns TVC_OK when the last stage that ran (the refinement if there is
+ * one) ended with delta < tol; TVC_ENOTCONVERGED when it stopped at its
+ * sweep cap instead (the last iterate is still in x); TVC_EDEGENERATE; or an
  * argument error. */
 int32_t hopm_solve(const tvc_tensor* A, const tvc_tensor* A_refine, double* x,
                    double tol, int32_t max_sweeps, int32_t check_every,

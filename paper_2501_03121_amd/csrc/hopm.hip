@@ -1103,6 +1103,9 @@ int32_t hopm_solve(const tvc_tensor* A, const tvc_tensor* A_refine, double* x, d
   h.sweeps = done;
   int rdone = 0;
   if (A_refine && refine_sweeps > 0) {
+    // the refinement is the last stage: its own stopping test decides the
+    // status, whether or not the low-precision stage met tol
+    converged = false;
     hopm_stats hr{};
     while (rdone < refine_sweeps) {
       const int k = std::min(check_every, refine_sweeps - rdone);
@@ -1119,12 +1122,17 @@ int32_t hopm_solve(const tvc_tensor* A, const tvc_tensor* A_refine, double* x, d
       }
       h.lambda = hr.lambda;
       h.delta = hr.delta;
-      if (hr.delta < tol) break;
+      if (hr.delta < tol) {
+        converged = true;
+        break;
+      }
     }
   }
   h.refine_sweeps = rdone;
   *h_out = h;
-  if (!converged) return fail(TVC_ENOTCONVERGED, "max_sweeps reached");
+  if (!converged)
+    return fail(TVC_ENOTCONVERGED, rdone ? "refine_sweeps reached before delta < tol"
+                                          : "max_sweeps reached before delta < tol");
   return TVC_OK;
 }
 

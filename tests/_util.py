@@ -44,3 +44,23 @@ def vec(n, seed, fmt, dev):
 
 def host(t):
     return t.detach().cpu().to(torch.float64).numpy()
+
+
+# unit roundoff of the accumulation type (float64 data accumulate in double,
+# every other format in float)
+UNIT = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "f16": 2.0 ** -24, "bf16": 2.0 ** -24,
+        "e4m3": 2.0 ** -24}
+
+
+def assert_elementwise(got, ref, ref_abs, n, fmt, what=""):
+    """Every output within the rounding bound of an n-term dot product in the
+    accumulation type: |got - ref| <= (2n + 8) u sum |a_i x_i| (ref_abs is
+    that sum of magnitudes, from the oracle on |A| and |x|).  Any summation
+    order meets it, so a single wrong output cannot hide under a norm."""
+    got = np.asarray(got, dtype=np.float64).reshape(-1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(-1)
+    ref_abs = np.asarray(ref_abs, dtype=np.float64).reshape(-1)
+    bound = (2 * n + 8) * UNIT[fmt] * ref_abs + 1e-300
+    bad = np.flatnonzero(np.abs(got - ref) > bound)
+    assert bad.size == 0, (what, fmt, int(bad.size), int(bad[0]), float(got[bad[0]]),
+                           float(ref[bad[0]]), float(bound[bad[0]]))

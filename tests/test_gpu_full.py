@@ -61,16 +61,19 @@ def test_full_size_hopm_sweep(dev, dims):
 @pytest.mark.timeout(600)
 def test_full_size_bf16_lambda_error(dev):
     # 32^6 planted tensor: float64 oracle solve from the warm start vs the
-    # bf16-storage solve with one float32 refinement sweep
+    # bf16-storage solve, then float32 refinement sweeps to the same tol
     dims = SHAPES[1]
     A, a = synth.device_planted(dims, 10.0, 0.1, 200, dev)
     x0 = synth.warm_start(a, 0.9, 400)
     ref = H.hopm(A.cpu().numpy(), x0, tol=1e-6, max_sweeps=40)
     Ab, _ = tvc.quantize(A, "bf16")
     x = tvc.pack_vectors(x0, dev)
-    r = tvc.hopm_solve(Ab, x, tol=1e-6, max_sweeps=200, A_refine=A, refine_sweeps=1)
-    assert r.status == 0
+    r = tvc.hopm_solve(Ab, x, tol=1e-6, max_sweeps=200)
+    assert r.status == 0 and r.delta < 1e-6
     assert abs(r.lam - ref.lam) <= 1e-3 * ref.lam
+    r = tvc.hopm_solve(Ab, x, tol=1e-6, max_sweeps=200, A_refine=A, refine_sweeps=60)
+    assert r.status == 0 and r.delta < 1e-6 and r.refine_sweeps >= 1
+    assert abs(r.lam - ref.lam) <= 1e-5 * ref.lam
     x = tvc.pack_vectors(x0, dev)
     r32 = tvc.hopm_solve(A, x, tol=1e-6, max_sweeps=200)
     assert abs(r32.lam - ref.lam) <= 1e-5 * ref.lam

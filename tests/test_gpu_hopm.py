@@ -127,13 +127,39 @@ def test_degenerate_zero_tensor(dev):
 
 
 def test_bf16_with_fp32_refinement(dev):
+    # the refinement runs to tol on the float32 data: its stopping test gives
+    # the status, and lambda then matches the float64 oracle to float32 level
     dims = (40, 36, 32)
     A, a = synth.planted_rank1(dims, 8.0, 0.05, 60, noise_kind="normal", vec_kind="normal")
     A32 = torch.from_numpy(A.astype(np.float32)).to(dev)
     Ab, _ = tvc.quantize(A32, "bf16")
     x0 = synth.unit_vectors(dims, 63)
     x = tvc.pack_vectors(x0, dev)
-    r = tvc.hopm_solve(Ab, x, tol=1e-6, max_sweeps=300, A_refine=A32, refine_sweeps=1)
-    assert r.status == 0 and r.refine_sweeps == 1
+    r = tvc.hopm_solve(Ab, x, tol=1e-6, max_sweeps=300, A_refine=A32, refine_sweeps=100)
+    assert r.status == 0 and r.delta < 1e-6 and 1 <= r.refine_sweeps < 100
     ref = H.hopm(A32.cpu().double().numpy(), x0, tol=1e-10, max_sweeps=2000)
-    assert abs(r.lam - ref.lam) <= 1e-3 * ref.lam
+    assert abs(r.lam - ref.lam) <= 1e-5 * ref.lam
+    got = np.split(host(x), np.cumsum(dims)[:-1])
+    for g, e in zip(got, ref.xs):
+        assert np.linalg.norm(g - e) < 1e-4
+
+
+def test_refinement_status_is_the_last_stage(dev):
+    dims = (40, 36, 32)
+    A, a = synth.planted_rank1(dims, 8.0, 0.05, 60, noise_kind="normal", vec_kind="normal")
+    A32 = torch.from_numpy(A.astype(np.float32)).to(dev)
+    Ab, _ = tvc.quantize(A32, "bf16")
+    x0 = synth.unit_vectors(dims, 63)
+    # a refinement cut off at one sweep has not met tol: not converged, even
+    # though the bf16 stage converged
+    x = tvc.pack_vectors(x0, dev)
+    r = tvc.hopm_solve(Ab, x, tol=1e-6, max_sweeps=300, A_refine=A32, refine_sweeps=1)
+    assert r.status == 7 and r.refine_sweeps == 1 and r.delta >= 1e-6
+    # a bf16 stage cut off at its cap, then a refinement that converges: ok
+    x = tvc.pack_vectors(x0, dev)
+    r = tvc.hopm_solve(Ab, x, tol=1e-6, max_sweeps=2, A_refine=A32, refine_sweeps=200)
+    assert r.status == 0 and r.sweeps == 2 and r.delta < 1e-6
+    # refine_sweeps = 0: no refinement, the first stage decides
+    x = tvc.pack_vectors(x0, dev)
+    r = tvc.hopm_solve(Ab, x, tol=1e-6, max_sweeps=2, A_refine=A32, refine_sweeps=0)
+    assert r.status == 7 and r.refine_sweeps == 0
