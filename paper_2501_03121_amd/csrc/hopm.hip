@@ -209,11 +209,11 @@ constexpr int kTailThreads = 512;
 constexpr int kTailElems = 2048;
 constexpr int kTailMaxSteps = 24;
 constexpr int kTailLds = 3;
-enum TailOp { kTLast = 0, kTFirst = 1, kTNorm = 2, kTKron = 3 };
+enum TailOp { kTLast = 0, kTFirst = 1, kTNorm = 2, kTKron = 3, kTCopy = 4 };
 
 struct TailStep {
   int op, src, dst, mode, flags;
-  i64 a, b;   // kTLast: rows, n; kTFirst: n, rest; kTNorm: n; kTKron: n0, n1
+  i64 a, b;   // kTLast: rows, n; kTFirst: n, rest; kTNorm: n; kTKron: n0, n1; kTCopy: n
 };
 
 template <typename Acc>
@@ -321,6 +321,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailProg<Acc> p) {
           }
         }
       }
+    } else if (q.op == kTCopy) {
+      for (i64 i = tid; i < q.a; i += kTailThreads) out[i] = in[i];
     } else {  // kTKron: out[r] = x_0[r / n1] * x_1[r mod n1] (* scale0[r / sdiv])
       const i64 n0 = q.a, n1 = q.b;
       const double* x0 = p.x + p.off[0];
@@ -631,6 +633,10 @@ struct Tail {
     const int flags = (j == 0 ? kFirstJ : 0) | (j == Lt.d - 1 ? kLastJ : 0);
     return add(kTNorm, &src, nullptr, j, flags, Lt.n[j], 0);
   }
+  tvc_status copy(const TBuf& src, const TBuf& dst) {
+    return add(kTCopy, &src, &dst, 0, 0, src.size, 0);
+  }
+  int room() const { return kTailMaxSteps - p.nsteps; }
   tvc_status kron(const TBuf& dst, i64 n0, i64 n1, const float* scale0, i64 sdiv) {
     p.scale0 = scale0;
     p.sdiv = sdiv;
@@ -701,6 +707,19 @@ tvc_status sweep(const Ctx& c) {
   TBuf W = TBuf::global(Wa, Lt.R1);
   Acc* wfree = Wb;   // the global W buffer not holding W
   for (int j = 2; j < d; ++j) {
+    // j's steps (at most one contraction of W, d - 1 - j of the chain and the
+    // normalisation) stay in one program, since they pass values through LDS.
+    // If they do not fit the pending program, it is run first; W moves to a
+    // global buffer beforehand when it lives in LDS (high orders, small dims).
+    if (tl.room() < (j > 2 ? 1 : 0) + (d - 1 - j) + 1 + 1) {   // + 1: the copy of W
+      if (!W.is_global()) {
+        const TBuf dst = TBuf::global(Wa, W.size);
+        TVC_TRY(tl.copy(W, dst));
+        W = dst;
+        wfree = Wb;
+      }
+      TVC_TRY(tl.flush());
+    }
     if (j > 2) {   // W_j = W_{j-1} contracted over its first mode (j - 1)
       const i64 out = W.size / n[j - 1];
       if (W.is_global() && W.size > kTailIn) {

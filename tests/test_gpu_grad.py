@@ -99,7 +99,8 @@ def test_rank_update(dev, dtype, dims, R):
     assert O.rel_err(host(D2), ref) < tol
 
 
-@pytest.mark.parametrize("dims,K", [((5, 4, 3), 4), ((12, 12, 12, 12), 10), ((6, 5, 4, 3, 2), 3), ((20, 30), 5)])
+@pytest.mark.parametrize("dims,K", [((5, 4, 3), 4), ((12, 12, 12, 12), 10), ((6, 5, 4, 3, 2), 3), ((20, 30), 5),
+                                    ((4, 3, 2, 3, 2, 3, 2), 3), ((2, 3, 2, 2, 3, 2, 2, 3, 2), 2)])
 def test_unrolled_hopm_grad_fp64_vs_oracle(dev, dims, K):
     Ah = synth.normal(dims, 11)
     x0 = synth.unit_vectors(dims, 12)

@@ -97,7 +97,7 @@ def check_against_oracle(traj, exact, x0, tol, form="chain"):
 
 
 @pytest.mark.parametrize("fmt", ["f64", "f32"])
-@pytest.mark.parametrize("dims", HIGH_ORDER[:4], ids=lambda d: f"order{len(d)}")
+@pytest.mark.parametrize("dims", HIGH_ORDER, ids=lambda d: f"order{len(d)}")
 def test_hopm_high_order_trajectory(dev, fmt, dims):
     A, _, exact = stored_tensor(dims, fmt, 19, dev, kind="normal")
     x0 = synth.unit_vectors(dims, 20)
