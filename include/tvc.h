@@ -117,6 +117,20 @@ int32_t tvc_contract(const tvc_tensor* A, int32_t mode, const void* x, void* y,
                      double alpha, double beta, void* ws, size_t ws_bytes,
                      void* stream);
 
+/* tvc_contract without a workspace argument, for callers that cannot
+ * allocate device memory (code under hipGraph capture, serving loops that
+ * forbid allocation): the scratch lives in a fixed device array of
+ * tvc_contract_noalloc_max_scratch() bytes (8 MiB) that the library holds on
+ * each device it runs on, until the process ends.  Makes no allocation.
+ * Same arguments, results and errors as tvc_contract, plus EWORKSPACE when
+ * tvc_contract_workspace_bytes(A, mode) exceeds that size (the contraction
+ * is not run).  Every call on one device shares that device's array: calls
+ * that overlap in time on one device (two streams, two threads) race and
+ * must not be made; calls in order on one stream are safe. */
+size_t tvc_contract_noalloc_max_scratch(void);
+int32_t tvc_contract_noalloc(const tvc_tensor* A, int32_t mode, const void* x, void* y,
+                             double alpha, double beta, void* stream);
+
 /* Introspection of the launch tvc_contract(A, mode, ...) would make, for
  * tests, benchmarks and the autotuner.  Writes up to n values to info (host):
  * [0] family (0 = rows of the right-extent-1 view, 1 = column streaming,

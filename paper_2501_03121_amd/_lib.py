@@ -89,6 +89,9 @@ SIGNATURES = {
     "tvc_contract_workspace_bytes": (c_size_t, [POINTER(TvcTensor), c_int32]),
     "tvc_contract": (c_int32, [POINTER(TvcTensor), c_int32, c_void_p, c_void_p, c_double, c_double,
                                c_void_p, c_size_t, c_void_p]),
+    "tvc_contract_noalloc_max_scratch": (c_size_t, []),
+    "tvc_contract_noalloc": (c_int32, [POINTER(TvcTensor), c_int32, c_void_p, c_void_p, c_double,
+                                       c_double, c_void_p]),
     "tvc_contract_plan": (c_int32, [POINTER(TvcTensor), c_int32, POINTER(c_int32), c_int32]),
     "hopm_workspace_bytes": (c_size_t, [POINTER(TvcTensor)]),
     "hopm_iterate": (c_int32, [POINTER(TvcTensor), c_void_p, c_int32, c_void_p, c_size_t, c_void_p,

@@ -20,6 +20,36 @@ std::mutex g_cu_mu;
 std::vector<int> g_cus;  // per device
 }  // namespace
 
+// Scratch of tvc_contract_noalloc: a fixed device array (each device the
+// library runs on holds its own copy until the process ends).  Host code
+// never passes the array's name to a kernel or a copy (on the host it only
+// stands for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device: address of `scratch` there
+
+tvc_status scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(TVC_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(TVC_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TVC_OK;
+}
+}  // namespace
+
 Tuning& tuning() {
   static Tuning t;
   return t;
@@ -204,6 +234,32 @@ int32_t tvc_contract(const tvc_tensor* A, int32_t mode, const void* x, void* y, 
   }
   return tvc_run_auto(A->dtype, A->data, L, M, R, w, y, alpha, beta, oscale, odiv,
                       wsleft ? (void*)wsp : nullptr, wsleft, st);
+}
+
+size_t tvc_contract_noalloc_max_scratch(void) { return kNoAllocScratchBytes; }
+
+int32_t tvc_contract_noalloc(const tvc_tensor* A, int32_t mode, const void* x, void* y,
+                             double alpha, double beta, void* stream) {
+  tvc_status s = check_tensor(A, "A");
+  if (s != TVC_OK) return s;
+  if (mode < 0 || mode >= A->order)
+    return fail(TVC_EINVAL, "mode " + std::to_string(mode) + " outside [0, order)");
+  i64 L, M, R;
+  mode_view(A, mode, &L, &M, &R);
+  const size_t need = contract_ws(A, mode, L, M, R);
+  if (need > kNoAllocScratchBytes)
+    return fail(TVC_EWORKSPACE, "this contraction needs " + std::to_string(need) +
+                                    " bytes of scratch, above the " +
+                                    std::to_string(kNoAllocScratchBytes) +
+                                    " bytes tvc_contract_noalloc holds; use tvc_contract");
+  void* p = nullptr;
+  if (need > 0) {
+    s = scratch_address(&p);
+    if (s != TVC_OK) return s;
+  }
+  // the kernels write every scratch value they read (split partials are
+  // stored whole before the finalize pass adds them): nothing to clear
+  return tvc_contract(A, mode, x, y, alpha, beta, p, need > 0 ? kNoAllocScratchBytes : 0, stream);
 }
 
 int32_t tvc_set_tuning(int32_t family, int32_t blocks_per_cu, int32_t split_m) {
