@@ -20,6 +20,10 @@ sum_{l,r} A[l,m,r] wl[l] wr[r] on the (u, n_j, v) view with Kronecker weight
 vectors (two matrix-vector products, blocked for tensors too large to upcast
 whole); `hopm(..., form="kron")` uses it for tensors of 10^9 elements and more.
 
+`jacobi_hopm` is the Jacobi variant (every vector of a sweep from the previous
+sweep's vectors), which the paper does not use; it is the oracle of the
+library's one-pass Jacobi sweep.
+
 `dhopm3` follows Algorithm 1 (dHOPM_3) at one process: three buffers, with the
 buffer W carried from j to j+1 for j >= 1.  It is a schedule model, used to
 check the contraction count (d-1)(d+2)/2 per sweep and that it reaches the
@@ -198,6 +202,50 @@ def _hopm_kron(A: np.ndarray, xs0: Sequence[np.ndarray], sweeps: int | None,
             if nrm == 0.0:
                 raise DegenerateError(f"zero-norm contraction at j={j}")
             xs[j] = y / nrm
+            res.norms.append(nrm)
+        res.lam = res.norms[-1]
+        res.sweeps += 1
+        delta = max(float(np.linalg.norm(xs[j] - old[j])) for j in range(d))
+        res.deltas.append(delta)
+        res.lams.append(res.lam)
+        if sweeps is None and tol is not None and delta < tol:
+            break
+    res.xs = xs
+    return res
+
+
+def jacobi_hopm(A: np.ndarray, xs0: Sequence[np.ndarray], sweeps: int | None = None,
+                tol: float | None = None, max_sweeps: int = 1000, form: str = "chain",
+                workers: int = 1) -> HopmResult:
+    """Jacobi variant of HOPM in float64 (not the paper's sweep, which is
+    Gauss-Seidel): in every sweep, y_j = A contracted with x_m for every
+    m != j is formed for all j from the vectors of the PREVIOUS sweep, and
+    only then x_j = s_j y_j / ||y_j|| with s_j = -1 when <y_j, x_j(old)> < 0,
+    else 1 (reading: the sign keeps each vector's orientation from sweep to
+    sweep; the directions are those of the plain Jacobi iteration, and
+    without it the signs of an even-order iteration can alternate forever).
+    lambda = ||y_{d-1}||, delta as in `hopm`.  form / workers as in `hopm`.
+    """
+    A = np.asarray(A)
+    d = A.ndim
+    if d < 2:
+        raise ValueError("HOPM needs order >= 2")
+    A64 = np.asarray(A, dtype=np.float64) if form == "chain" else A
+    xs = [np.asarray(x, dtype=np.float64).reshape(-1).copy() for x in xs0]
+    res = HopmResult(xs=xs, lam=0.0, sweeps=0)
+    limit = sweeps if sweeps is not None else max_sweeps
+    for _ in range(limit):
+        old = [x.copy() for x in xs]
+        if form == "kron":
+            ys = [leave_one_out_kron(A64, old, j, workers=workers) for j in range(d)]
+        else:
+            ys = [leave_one_out(A64, old, j) for j in range(d)]
+        for j in range(d):
+            nrm = float(np.linalg.norm(ys[j]))
+            if nrm == 0.0:
+                raise DegenerateError(f"zero-norm contraction at j={j}")
+            sign = -1.0 if float(np.dot(ys[j], old[j])) < 0.0 else 1.0
+            xs[j] = sign * ys[j] / nrm
             res.norms.append(nrm)
         res.lam = res.norms[-1]
         res.sweeps += 1

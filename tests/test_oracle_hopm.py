@@ -179,3 +179,62 @@ def test_kron_form_hopm_equals_chain(dims):
     k32 = H.hopm(A32, x0, sweeps=2, form="kron")
     k64 = H.hopm(A32.astype(np.float64), x0, sweeps=2, form="kron")
     np.testing.assert_array_equal(k32.norms, k64.norms)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5])
+def test_jacobi_matrix_case_is_two_power_iterations(k):
+    # d = 2: x_0 after 2k Jacobi sweeps is (A A^T)^k x_0 normalised (up to sign)
+    A = synth.normal((11, 8), 51)
+    x0 = synth.unit_vectors((11, 8), 52)
+    r = H.jacobi_hopm(A, x0, sweeps=2 * k)
+    v0 = np.linalg.matrix_power(A @ A.T, k) @ x0[0]
+    v1 = np.linalg.matrix_power(A.T @ A, k) @ x0[1]
+    assert abs(abs(np.dot(r.xs[0], v0 / np.linalg.norm(v0))) - 1) < 1e-12
+    assert abs(abs(np.dot(r.xs[1], v1 / np.linalg.norm(v1))) - 1) < 1e-12
+
+
+@pytest.mark.parametrize("dims", [(6, 5, 4), (3, 4, 5, 2), (4, 3, 3, 2, 3), (5, 7)])
+def test_jacobi_exact_rank1(dims):
+    a = synth.unit_vectors(dims, 61)
+    T = np.ones(())
+    for v in a:
+        T = np.multiply.outer(T, v)
+    r = H.jacobi_hopm(7.5 * T, synth.unit_vectors(dims, 62), sweeps=3)
+    for x, v in zip(r.xs, a):
+        assert abs(abs(np.dot(x, v)) - 1.0) < 1e-12
+    # every vector is +-a_j after one sweep; the sign choice keeps it still
+    assert r.deltas[1] < 1e-12 and r.deltas[2] < 1e-12
+    assert abs(r.lams[1] - 7.5) < 1e-12
+
+
+@pytest.mark.parametrize("dims", [(5, 4, 6), (3, 4, 2, 3)])
+def test_jacobi_first_sweep_uses_previous_vectors(dims):
+    A = synth.normal(dims, 71)
+    x0 = synth.unit_vectors(dims, 72)
+    r = H.jacobi_hopm(A, x0, sweeps=1)
+    for j in range(len(dims)):
+        y = _loo_brute(A, x0, j)
+        y = y / np.linalg.norm(y)
+        if np.dot(y, x0[j]) < 0:
+            y = -y
+        np.testing.assert_allclose(r.xs[j], y, rtol=1e-12, atol=1e-13)
+    # the Gauss-Seidel sweep differs after j = 0
+    g = H.hopm(A, x0, sweeps=1)
+    np.testing.assert_allclose(g.xs[0], r.xs[0] * np.sign(np.dot(g.xs[0], r.xs[0])), rtol=1e-12)
+    assert np.linalg.norm(np.abs(g.xs[1]) - np.abs(r.xs[1])) > 1e-6
+
+
+@pytest.mark.parametrize("dims", [(12, 10, 9), (6, 5, 7, 4)])
+def test_jacobi_reaches_the_gauss_seidel_fixed_point(dims):
+    A, a = synth.planted_rank1(dims, 6.0, 0.05, 81, noise_kind="normal")
+    x0 = synth.unit_vectors(dims, 82)
+    gs = H.hopm(A, x0, tol=1e-13, max_sweeps=5000)
+    ja = H.jacobi_hopm(A, x0, tol=1e-13, max_sweeps=5000)
+    assert ja.deltas[-1] < 1e-13
+    assert abs(ja.lam - gs.lam) < 1e-11 * gs.lam
+    for u, v in zip(ja.xs, gs.xs):
+        assert abs(abs(np.dot(u, v)) - 1) < 1e-11
+    # kron form: same iterates
+    jk = H.jacobi_hopm(A, x0, sweeps=6, form="kron")
+    jc = H.jacobi_hopm(A, x0, sweeps=6)
+    np.testing.assert_allclose(jk.norms, jc.norms, rtol=1e-12)
