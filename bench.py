@@ -10,8 +10,12 @@ a contraction moves N*4 bytes of A plus its vector and output; a sweep moves
 before timing starts.
 
 Printed: one JSON line (the last line of stdout).  Extra fields report the
-per-mode figures, bf16 storage, time to solution, the bandwidth probe, the
-dominant kernel against the HBM roofline and the float64 CPU oracle.
+per-mode figures, the narrow storage formats, float64 at the same shapes,
+time to solution (float32, bf16, fp16, E4M3, bf16 with float32 refinement,
+Jacobi sweeps) with every result's error against the float64 oracle, the
+looped rocBLAS comparator, the bandwidth probe, derivatives, the batch, the
+paper's Table 1 tensors, the dominant kernel against the HBM roofline and
+the float64 CPU oracle.
 """
 from __future__ import annotations
 
@@ -85,6 +89,7 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--calib", action="store_true",
                     help="only run the read/copy probes of known size (counter calibration)")
+    ap.add_argument("--no-table1", action="store_true", help="skip the Table 1 leg of the extras")
     ap.add_argument("--table1", action="store_true",
                     help="only the hypersquare tensors of the paper's Table 1 (orders 2-10, float32): "
                          "contraction in every mode and one HOPM sweep, %% of peak mean and std per order")
@@ -101,6 +106,8 @@ def main() -> int:
     from paper_2501_03121_amd import _lib as L
     from paper_2501_03121_amd import core, synth
 
+    global T0
+    T0 = time.perf_counter()
     dev = torch.device("cuda:0")
     lib = L.lib()
     stream = torch.cuda.current_stream()
@@ -234,6 +241,7 @@ def main() -> int:
 
     if not args.no_extras:
         extra.update(run_extras(T, Hs, planted, dev, args))
+    extra["bench_wall_s"] = round(time.perf_counter() - T0, 1)
 
     result = {
         "metric": METRIC,
@@ -254,10 +262,241 @@ def main() -> int:
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(T)
+        result["cpu_baseline"] = cpu_baseline(T, extra.get("time_to_solution"))
     result["extra"] = extra
     print(json.dumps(result), flush=True)
     return 0
+
+
+def timed_ms(fn, reps, warm=1):
+    """Median of `reps` single calls, each bracketed by events on the current
+    stream (the queue stays full, so host launch latency is not counted)."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    return median_ms(fn, reps)
+
+
+class Rocblas:
+    """rocBLAS (the vendor BLAS of ROCm) through ctypes: the looped
+    formulation of the contraction the paper compares against (Sec. 3: a
+    batch of matrix-vector products over the (u, n_k, v) view, one per
+    left index), here rocblas_[sd]gemv_strided_batched_64 on torch's stream."""
+    NONE, TRANS = 111, 112
+    MAX_BATCH = 32768
+    MAX_COLS = 1 << 20
+
+    def __init__(self, stream_handle):
+        path = "/opt/rocm/lib/librocblas.so"
+        self.lib = ctypes.CDLL(path)
+        h = ctypes.c_void_p()
+        self._ok(self.lib.rocblas_create_handle(ctypes.byref(h)))
+        self.h = h
+        self._ok(self.lib.rocblas_set_stream(h, ctypes.c_void_p(stream_handle)))
+        i64, vp = ctypes.c_int64, ctypes.c_void_p
+        for name in ("rocblas_sgemv_strided_batched_64", "rocblas_dgemv_strided_batched_64"):
+            fn = getattr(self.lib, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = [vp, ctypes.c_int, i64, i64, vp, vp, i64, i64, vp, i64, i64, vp, vp, i64, i64, i64]
+
+    @staticmethod
+    def _ok(st):
+        if st != 0:
+            # a failed launch leaves HIP's last-error state set; clear it so
+            # that later calls do not report it
+            try:
+                ctypes.CDLL("libamdhip64.so").hipGetLastError()
+            except OSError:
+                pass
+            raise RuntimeError(f"rocBLAS status {st}")
+
+    def contract(self, A, x, k, y):
+        """y = A x_k x as looped matrix-vector products on the (u, n_k, v) view."""
+        import torch
+        dims = tuple(A.shape)
+        u = math.prod(dims[:k])
+        n = dims[k]
+        v = math.prod(dims[k + 1:])
+        f64 = A.dtype == torch.float64
+        one = (ctypes.c_double if f64 else ctypes.c_float)(1.0)
+        zero = (ctypes.c_double if f64 else ctypes.c_float)(0.0)
+        fn = self.lib.rocblas_dgemv_strided_batched_64 if f64 else self.lib.rocblas_sgemv_strided_batched_64
+        eb = A.element_size()
+        if v == 1:      # y[l] = sum_m A[l, m] x[m]: A is column-major n x u, transposed
+            # (in launches of at most MAX_COLS columns: rocBLAS's kernel for
+            # this case has one workgroup per column)
+            for l0 in range(0, u, self.MAX_COLS):
+                b = min(self.MAX_COLS, u - l0)
+                self._ok(fn(self.h, self.TRANS, n, b, ctypes.byref(one), A.data_ptr() + l0 * n * eb, n, 0,
+                            x.data_ptr(), 1, 0, ctypes.byref(zero), y.data_ptr() + l0 * eb, 1, 0, 1))
+            return
+        # per left index l: y_l = A_l x with A_l column-major v x n; the
+        # batch goes in launches of at most MAX_BATCH matrices (the batch
+        # index is a grid dimension of rocBLAS's kernels)
+        for l0 in range(0, u, self.MAX_BATCH):
+            b = min(self.MAX_BATCH, u - l0)
+            self._ok(fn(self.h, self.NONE, v, n, ctypes.byref(one), A.data_ptr() + l0 * n * v * eb, v, n * v,
+                        x.data_ptr(), 1, 0, ctypes.byref(zero), y.data_ptr() + l0 * v * eb, 1, v, b))
+
+
+def run_looped(tensors, shapes, dev, reps=5):
+    """Per-mode %-of-peak of the looped rocBLAS contraction beside the
+    library's, on the same tensors and vectors; each output checked against
+    the library's."""
+    import torch
+
+    import paper_2501_03121_amd as tvc
+    from paper_2501_03121_amd import synth
+    rb = Rocblas(torch.cuda.current_stream().cuda_stream)
+    out = {}
+    for A, dims in zip(tensors, shapes):
+        b_a = A.element_size()
+        acc = torch.float64 if A.dtype == torch.float64 else torch.float32
+        for k in range(len(dims)):
+            x = torch.from_numpy(synth.unit_vectors([dims[k]], 300 + k)[0]).to(acc).to(dev)
+            y = torch.empty(A.numel() // dims[k], dtype=acc, device=dev)
+            yl = torch.empty_like(y)
+            ms_n = timed_ms(lambda: tvc.contract(A, x, k, out=y), reps)
+            nb = tvc_bytes(dims, k, b_a, acc.itemsize)
+            rec = {"native_pct": round(100 * nb / (ms_n * 1e-3) / 1e9 / PEAK_HBM_GBS, 1),
+                   "native_ms": round(ms_n, 4)}
+            try:
+                ms_l = timed_ms(lambda: rb.contract(A, x, k, yl), reps)
+                err = float(torch.linalg.vector_norm((y - yl).double()) / torch.linalg.vector_norm(y.double()))
+                rec.update({"looped_pct": round(100 * nb / (ms_l * 1e-3) / 1e9 / PEAK_HBM_GBS, 1),
+                            "looped_ms": round(ms_l, 4), "rel_diff": err})
+            except RuntimeError as e:
+                rec["looped_error"] = str(e)
+            out[f"{len(dims)}d_{dims[0]}_mode{k}"] = rec
+            del y, yl
+    nat = [v["native_pct"] for v in out.values()]
+    loo = [v.get("looped_pct") for v in out.values()]
+    return {"per_mode": out,
+            "native_mean_std": [round(statistics.mean(nat), 1), round(statistics.stdev(nat), 1)],
+            "looped_mean_std": [_mean(loo), _std(loo)]}
+
+
+def run_fp64(dev, reps=5):
+    """float64 storage at the benchmark shapes (8.6 GB each): contraction in
+    every mode and one HOPM sweep, % of peak (the paper's Tables 2 and 3 are
+    float64)."""
+    import torch
+
+    import paper_2501_03121_amd as tvc
+    from paper_2501_03121_amd import synth
+    out = {}
+    for i, dims in enumerate(SHAPES):
+        A = synth.device_normal(dims, 700 + i, dev, dtype=torch.float64)
+        per = {}
+        for k in range(len(dims)):
+            x = torch.from_numpy(synth.unit_vectors([dims[k]], 300 + k)[0]).to(dev)
+            y = torch.empty(A.numel() // dims[k], dtype=torch.float64, device=dev)
+            ms = timed_ms(lambda: tvc.contract(A, x, k, out=y), reps)
+            per[f"mode{k}"] = round(100 * tvc_bytes(dims, k, 8, 8) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 1)
+            del y
+        x = tvc.pack_vectors(synth.unit_vectors(dims, 60), dev)
+        ms = timed_ms(lambda: tvc.hopm_iterate(A, x, 1), reps)
+        vals = list(per.values())
+        out[f"{len(dims)}d_{dims[0]}"] = {"tvc_pct_per_mode": per, "tvc_pct_mean": round(statistics.mean(vals), 1),
+                                          "tvc_pct_std": round(statistics.stdev(vals), 1),
+                                          "sweep_ms": round(ms, 3),
+                                          "sweep_pct": round(100 * sweep_bytes(dims, 8) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 1)}
+        del A
+        torch.cuda.empty_cache()
+    return out
+
+
+def run_probe(src, dev):
+    """The library's read and copy probes (contiguous range per workgroup,
+    nontemporal 16-byte accesses): the best of several grid sizes is the
+    achievable rate the contraction kernels are also set against."""
+    import torch
+
+    import paper_2501_03121_amd as tvc
+    from paper_2501_03121_amd import _lib as L
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    sink = torch.empty(64 * cus, dtype=torch.float32, device=dev)
+    reads = {}
+    for g in (cus, 2 * cus, 4 * cus, 8 * cus, 16 * cus):
+        ms = timed_ms(lambda: tvc.probe_read(src, sink, grid=g), 10)
+        reads[g] = src.numel() * src.element_size() / (ms * 1e-3) / 1e9
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    ms = timed_ms(lambda: tvc.probe_copy(a, b), 10)
+    cp = 2 * a.numel() * 4 / (ms * 1e-3) / 1e9
+    del a, b
+    best = max(reads.values())
+    return {"read_GBps": round(best, 1), "read_pct_peak": round(100 * best / PEAK_HBM_GBS, 1),
+            "read_GBps_by_grid": {str(g): round(v, 1) for g, v in reads.items()},
+            "copy_GBps": round(cp, 1), "bytes_read": src.numel() * src.element_size()}
+
+
+def oracle_solve(A, x0, tol, workers=16):
+    """The float64 oracle's Gauss-Seidel HOPM (multilinear form) from the
+    exact host copy of A and the same start vectors."""
+    from oracle import hopm as H
+    Ah = A.cpu().numpy()
+    t0 = time.perf_counter()
+    ref = H.hopm(Ah, x0, tol=tol, max_sweeps=500, form="kron", workers=workers)
+    return ref, time.perf_counter() - t0
+
+
+def run_tts(Hs, planted, dev, tol=1e-6, reps=3):
+    """Time to solution (delta < tol, one readback per sweep) from the same
+    warm start (overlap 0.9 with the planted vectors), for every storage
+    format, bf16 followed by float32 refinement to the same tol, and Jacobi
+    sweeps; each result's lambda and vector error against the float64
+    oracle's solution from the same start on the original float32 data
+    (computed outside the timed region)."""
+    import numpy as np
+    import torch
+
+    import paper_2501_03121_amd as tvc
+    from paper_2501_03121_amd import synth
+    tts = {}
+    for i, (A, s) in enumerate(zip(Hs, SHAPES)):
+        x0 = synth.warm_start(planted[i], 0.9, 400 + i)
+        ref, oracle_s = oracle_solve(A, x0, tol)
+        stores = {"f32": (A, None)}
+        for fmt in ("bf16", "f16", "e4m3"):
+            stores[fmt] = tvc.quantize(A, fmt)
+        runs = [("f32", "f32", None, "gs"), ("bf16", "bf16", None, "gs"), ("f16", "f16", None, "gs"),
+                ("e4m3", "e4m3", None, "gs"), ("bf16+f32refine", "bf16", A, "gs"),
+                ("f32_jacobi", "f32", None, "jacobi"), ("bf16_jacobi", "bf16", None, "jacobi")]
+        res = {}
+        for label, fmt, refine, method in runs:
+            Aq, S = stores[fmt]
+            times = []
+            for _ in range(reps):
+                x = tvc.pack_vectors(x0, dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if method == "jacobi":
+                    r = tvc.hopm_jacobi_solve(Aq, x, tol=tol, max_sweeps=1000, scale=S)
+                else:
+                    r = tvc.hopm_solve(Aq, x, tol=tol, max_sweeps=500, check_every=1, scale=S,
+                                       A_refine=refine, refine_sweeps=100 if refine is not None else 0)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            got = np.split(x.cpu().numpy(), np.cumsum(s)[:-1])
+            verr = max(min(np.linalg.norm(g - e), np.linalg.norm(g + e)) for g, e in zip(got, ref.xs))
+            res[label] = {"seconds": round(statistics.median(times), 5), "sweeps": r.sweeps,
+                          "refine_sweeps": r.refine_sweeps, "status": r.status, "delta": r.delta,
+                          "lambda": r.lam, "lambda_rel_err_vs_oracle": abs(r.lam - ref.lam) / ref.lam,
+                          "vector_err_vs_oracle": float(verr),
+                          "min_overlap_planted": round(min(abs(float(g @ a)) for g, a in zip(got, planted[i])), 6)}
+        f32 = res["f32"]["seconds"]
+        res["speedup_vs_f32"] = {k: round(f32 / v["seconds"], 3) for k, v in res.items() if k != "f32"}
+        res["oracle"] = {"lambda": ref.lam, "sweeps": ref.sweeps, "seconds": round(oracle_s, 2),
+                         "form": "multilinear, float64, 16 threads"}
+        tts[f"{len(s)}d_{s[0]}"] = res
+        log(json.dumps({f"{len(s)}d_{s[0]}": {lbl: [v["seconds"], v["sweeps"], v["refine_sweeps"], v["status"],
+                                                     v["lambda_rel_err_vs_oracle"]]
+                                               for lbl, v in res.items() if "refine_sweeps" in v},
+                        "speedup_vs_f32": res["speedup_vs_f32"], "oracle": res["oracle"]}))
+        del stores
+    return tts
 
 
 def run_extras(T, Hs, planted, dev, args):
@@ -267,34 +506,9 @@ def run_extras(T, Hs, planted, dev, args):
     from paper_2501_03121_amd import synth
 
     out = {}
-    # bandwidth probe: read the 1024^3 tensor, copy 1 GiB
-    sink = torch.empty(8192, dtype=torch.float32, device=dev)
-    src = T[0]
-    for _ in range(2):
-        tvc.probe_read(src, sink)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 10
-    e0.record()
-    for _ in range(reps):
-        tvc.probe_read(src, sink)
-    e1.record()
-    torch.cuda.synchronize()
-    rd = src.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-    b = torch.empty_like(a)
-    tvc.probe_copy(a, b)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        tvc.probe_copy(a, b)
-    e1.record()
-    torch.cuda.synchronize()
-    cp = 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del a, b
-    out["probe"] = {"read_GBps": round(rd, 1), "copy_GBps": round(cp, 1),
-                    "read_pct_peak": round(100 * rd / PEAK_HBM_GBS, 1)}
+    out["probe"] = run_probe(T[0], dev)
     log(json.dumps(out["probe"]))
+    ach = out["probe"]["read_GBps"]
 
     # narrow storage: every-mode contraction in bf16, fp16 and E4M3 (+ slab scales)
     ebytes = {"bf16": 2, "f16": 2, "e4m3": 1}
@@ -305,59 +519,24 @@ def run_extras(T, Hs, planted, dev, args):
             for k in range(len(s)):
                 x = torch.from_numpy(synth.unit_vectors([s[k]], 300 + k)[0]).float().to(dev)
                 y = torch.empty(A.numel() // s[k], dtype=torch.float32, device=dev)
-                tvc.contract(Aq, x, k, out=y, scale=S)
-                torch.cuda.synchronize()
-                e0.record()
-                for _ in range(reps):
-                    tvc.contract(Aq, x, k, out=y, scale=S)
-                e1.record()
-                torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / reps
+                ms = timed_ms(lambda: tvc.contract(Aq, x, k, out=y, scale=S), 10)
                 gbs = tvc_bytes(s, k, b) / (ms * 1e-3) / 1e9
                 res[f"{len(s)}d_{s[0]}_mode{k}"] = {"ms": round(ms, 4), "GBps": round(gbs, 1),
-                                                    "pct_peak": round(100 * gbs / PEAK_HBM_GBS, 1)}
+                                                    "pct_peak": round(100 * gbs / PEAK_HBM_GBS, 1),
+                                                    "pct_of_probe": round(100 * gbs / ach, 1)}
             del Aq, S
         out[f"{fmt}_tvc"] = res
         log(json.dumps({fmt: res}))
 
-    # time to solution: float32 vs bf16 storage + one float32 refinement sweep,
-    # from the same warm start (overlap 0.9 with the planted vectors)
-    tts = {}
-    for i, (A, s) in enumerate(zip(Hs, SHAPES)):
-        Ab, _ = tvc.quantize(A, "bf16")
-        x0 = synth.warm_start(planted[i], 0.9, 400 + i)
-        res = {}
-        for label, store, refine in (("f32", A, None), ("bf16", Ab, None), ("bf16+f32refine", Ab, A)):
-            runs = []
-            for rep in range(3):
-                x = tvc.pack_vectors(x0, dev)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                r = tvc.hopm_solve(store, x, tol=1e-6, max_sweeps=500, check_every=1,
-                                   A_refine=refine, refine_sweeps=1 if refine is not None else 0)
-                torch.cuda.synchronize()
-                runs.append((time.perf_counter() - t0, r))
-            tmed = statistics.median(t for t, _ in runs)
-            r = runs[-1][1]
-            xs = x.cpu().numpy()
-            dims_off = 0
-            overl = []
-            for k, n in enumerate(s):
-                overl.append(abs(float(xs[dims_off:dims_off + n] @ planted[i][k])))
-                dims_off += n
-            res[label] = {"seconds": round(tmed, 5), "sweeps": r.sweeps, "refine_sweeps": r.refine_sweeps,
-                          "lambda": r.lam, "delta": r.delta, "status": r.status,
-                          "min_overlap": round(min(overl), 6)}
-        res["speedup_bf16_refined"] = round(res["f32"]["seconds"] / res["bf16+f32refine"]["seconds"], 3)
-        res["speedup_bf16_only"] = round(res["f32"]["seconds"] / res["bf16"]["seconds"], 3)
-        res["lambda_rel_diff_refined"] = abs(res["bf16+f32refine"]["lambda"] - res["f32"]["lambda"]) / res["f32"]["lambda"]
-        res["lambda_rel_diff_bf16_only"] = abs(res["bf16"]["lambda"] - res["f32"]["lambda"]) / res["f32"]["lambda"]
-        tts[f"{len(s)}d_{s[0]}"] = res
-        del Ab
-    out["time_to_solution"] = tts
-    log(json.dumps(tts))
+    out["f64"] = run_fp64(dev)
+    log(json.dumps({"f64": out["f64"]}))
+    out["looped_rocblas"] = run_looped(T, SHAPES, dev)
+    log(json.dumps({"looped": out["looped_rocblas"]}))
+    out["time_to_solution"] = run_tts(Hs, planted, dev)
     out["derivatives_256_4"] = run_derivatives(dev)
     out["batch"] = run_batch(dev)
+    if not args.no_table1:
+        out["table1"] = run_table1(dev)
     return out
 
 
@@ -380,36 +559,51 @@ def median_ms(fn, reps, e0=None, e1=None):
     return statistics.median(a.elapsed_time(b) for a, b in ev)
 
 
+def _mean(v):
+    v = [x for x in v if x is not None]
+    return round(statistics.mean(v), 1) if v else None
+
+
+def _std(v):
+    v = [x for x in v if x is not None]
+    return round(statistics.stdev(v), 1) if len(v) > 1 else None
+
+
 def run_table1(dev, reps: int = 5):
     """The paper's Table 1 hypersquare tensors (dims chosen not to be
     multiples of the vector length), here in float32 (same element counts,
-    3.3-4.3 GB): %-of-peak of the contraction in every mode and of one HOPM
-    sweep (median of `reps` timed calls each), with mean and unbiased std
-    over the modes (the Table 2 statistic)."""
+    3.3-4.3 GB): %-of-peak of the contraction in every mode, natively and
+    as looped rocBLAS matrix-vector products, and of one HOPM sweep (median
+    of `reps` timed calls each), with mean and unbiased std over the modes
+    (the Table 2 statistic); the canonical HOPM sweep and the one-pass
+    Jacobi sweep on the same tensor."""
     import torch
 
     import paper_2501_03121_amd as tvc
     from paper_2501_03121_amd import synth
 
+    rb = Rocblas(torch.cuda.current_stream().cuda_stream)
     out = {}
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for d, n in TABLE1.items():
         dims = (n,) * d
         A = synth.device_normal(dims, 40 + d, dev)
-        per = []
+        per, loo = [], []
         for k in range(d):
             x = torch.from_numpy(synth.unit_vectors([n], 50 + k)[0]).float().to(dev)
             y = torch.empty(A.numel() // n, dtype=torch.float32, device=dev)
-            tvc.contract(A, x, k, out=y)
-            torch.cuda.synchronize()
-            ms = median_ms(lambda: tvc.contract(A, x, k, out=y), reps, e0, e1)
+            ms = timed_ms(lambda: tvc.contract(A, x, k, out=y), reps)
             per.append(100 * tvc_bytes(dims, k, 4) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
+            try:
+                ms = timed_ms(lambda: rb.contract(A, x, k, y), reps)
+                loo.append(100 * tvc_bytes(dims, k, 4) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
+            except RuntimeError:
+                loo.append(None)
             del y
         x = tvc.pack_vectors(synth.unit_vectors(dims, 60), dev)
-        tvc.hopm_iterate(A, x, 1)
-        torch.cuda.synchronize()
-        ms = median_ms(lambda: tvc.hopm_iterate(A, x, 1), reps, e0, e1)
+        ms = timed_ms(lambda: tvc.hopm_iterate(A, x, 1), reps)
         sweep = 100 * sweep_bytes(dims, 4) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS
+        jms = timed_ms(lambda: tvc.hopm_jacobi_iterate(A, x, 1), reps)
+        jac = 100 * (math.prod(dims) * 4 + 8 * sum(dims)) / (jms * 1e-3) / 1e9 / PEAK_HBM_GBS
         # The canonical HOPM sweep of Sec. 3 on the same kernels: x_j is the
         # contraction of A with every other vector, one mode at a time (the
         # last modes first, so mode indices stay valid), then normalised;
@@ -425,19 +619,25 @@ def run_table1(dev, reps: int = 5):
                         T = tvc.contract(T, xs[i], i)
                 xs[j] = T / torch.linalg.vector_norm(T)
 
-        for _ in range(2):
-            canonical()
-        torch.cuda.synchronize()
-        cms = median_ms(canonical, 5, e0, e1)
+        cms = timed_ms(canonical, 5, warm=2)
         out[f"{n}^{d}"] = {"tvc_pct_mean": round(statistics.mean(per), 1),
                            "tvc_pct_std": round(statistics.stdev(per), 1) if d > 1 else 0.0,
                            "tvc_pct_per_mode": [round(p, 1) for p in per],
+                           "looped_pct_mean": _mean(loo),
+                           "looped_pct_std": _std(loo),
+                           "looped_pct_per_mode": [None if p is None else round(p, 1) for p in loo],
                            "sweep_ms": round(ms, 3), "sweep_pct": round(sweep, 1),
+                           "jacobi_sweep_ms": round(jms, 3), "jacobi_sweep_pct": round(jac, 1),
                            "canonical_sweep_ms": round(cms, 3),
                            "fused_sweep_speedup": round(cms / ms, 2)}
         log(json.dumps({f"{n}^{d}": out[f"{n}^{d}"]}))
         del A, x, xs
         torch.cuda.empty_cache()
+    allp = [p for v in out.values() for p in v["tvc_pct_per_mode"]]
+    alll = [p for v in out.values() for p in v["looped_pct_per_mode"]]
+    out["summary"] = {"tvc_pct_mean_std_all_modes": [round(statistics.mean(allp), 1), round(statistics.stdev(allp), 1)],
+                      "looped_pct_mean_std_all_modes": [_mean(alll), _std(alll)],
+                      "sweep_pct_mean": round(statistics.mean(v["sweep_pct"] for v in out.values()), 1)}
     return out
 
 
@@ -561,38 +761,82 @@ def run_batch(dev, count: int = 512, sweeps: int = 50):
     return out
 
 
-def cpu_baseline(tensors, budget_s: float = 15.0):
+def _host_info():
+    import numpy as np
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = []
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [{k: d.get(k) for k in ("internal_api", "version", "num_threads", "threading_layer")}
+                for d in threadpool_info() if d.get("user_api") == "blas"]
+    except Exception:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "numpy": np.__version__, "blas": blas}
+
+
+def cpu_baseline(tensors, tts=None, budget_s: float = 10.0):
     """The float64 oracle (NumPy) on the host: the contractions of the
-    benchmark step (every mode of the 1024^3 and 32^6 tensors), from the
-    exact upcast of the device bytes (upcast not timed), repeated until about
-    `budget_s` seconds of CPU work.  Throughput counts 4 bytes per element of
-    A, like the GPU figure."""
+    benchmark step (every mode of the 1024^3 and 32^6 tensors) from the exact
+    upcast of the device bytes (upcast not timed), repeated for about
+    `budget_s` seconds with all BLAS threads and again with one thread.
+
+    `value` counts the same algorithmic bytes as the GPU figure (4 bytes per
+    float32 element of A, so the two rates compare work done); the float64
+    bytes the oracle actually reads (8 per element) are reported beside it.
+    The oracle's HOPM time per sweep comes from the time-to-solution leg."""
     import numpy as np
 
     from oracle import tvc as O
     from paper_2501_03121_amd import synth
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max((d.get("num_threads", 1) for d in threadpool_info()), default=1)
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count() or 1
     log("cpu baseline: copying tensors to host")
     hosts = [A.cpu().numpy().astype(np.float64) for A in tensors]
-    t, nbytes, reps = 0.0, 0, 0
-    while t < budget_s and reps < 50:
-        for A in hosts:
-            for k in range(A.ndim):
-                x = synth.unit_vectors([A.shape[k]], 300 + k)[0]
-                t0 = time.perf_counter()
-                O.tvc(A, x, k)
-                t += time.perf_counter() - t0
-                nbytes += A.size * 4
-        reps += 1
+
+    def leg(budget):
+        # the nine contractions in turn until the budget is spent (at least one)
+        t, elems, calls = 0.0, 0, 0
+        work = [(A, k) for A in hosts for k in range(A.ndim)]
+        while t < budget and calls < 50 * len(work):
+            A, k = work[calls % len(work)]
+            x = synth.unit_vectors([A.shape[k]], 300 + k)[0]
+            t0 = time.perf_counter()
+            O.tvc(A, x, k)
+            t += time.perf_counter() - t0
+            elems += A.size
+            calls += 1
+        return t, elems, calls
+
+    t, elems, reps = leg(budget_s)
+    one = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1, user_api="blas"):
+            t1, e1, _ = leg(budget_s)
+        one = {"value": round(e1 * 4 / t1 / 1e9, 2), "fp64_read_GBps": round(e1 * 8 / t1 / 1e9, 2),
+               "cores": 1, "seconds": round(t1, 1), "elements": int(e1)}
     del hosts
-    gbs = nbytes / t / 1e9
-    return {"value": round(gbs, 2), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"float64 NumPy oracle: every-mode contraction of the 1024^3 and 32^6 "
-                      f"tensors, {reps} repetition(s), {t:.1f} s; 4 bytes per element counted"}
+    out = {"value": round(elems * 4 / t / 1e9, 2), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"float64 NumPy oracle: every-mode contraction of the 1024^3 and 32^6 tensors, "
+                     f"{reps} contraction(s) in turn, {t:.1f} s; value counts 4 bytes per "
+                     f"element (the float32 workload's algorithmic bytes), fp64_read_GBps the 8 bytes "
+                     f"per element the oracle reads",
+           "fp64_read_GBps": round(elems * 8 / t / 1e9, 2), "one_thread": one, "host": _host_info()}
+    if tts:
+        out["oracle_hopm_seconds_per_sweep"] = {
+            k: round(v["oracle"]["seconds"] / max(1, v["oracle"]["sweeps"]), 3) for k, v in tts.items()}
+    return out
 
 
 if __name__ == "__main__":

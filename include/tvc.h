@@ -194,6 +194,23 @@ int32_t hopm_solve(const tvc_tensor* A, const tvc_tensor* A_refine, double* x,
                    int32_t refine_sweeps, void* ws, size_t ws_bytes,
                    hopm_stats* h_out, void* stream);
 
+/* Jacobi HOPM, a variant of the method (not the paper's sweep, which is
+ * Gauss-Seidel): in every sweep each x_j is replaced by the normalised
+ * contraction of A with the OTHER vectors of the previous sweep, so all d
+ * contractions come from one pass over A (half the bytes of a Gauss-Seidel
+ * sweep; usually more sweeps to converge).  Each new x_j takes the sign that
+ * keeps <x_j(new), x_j(old)> >= 0 (the directions are those of the plain
+ * Jacobi iteration; without the choice, even orders can flip every sign in
+ * every sweep and delta would not fall).  Same arguments, workspace
+ * (hopm_workspace_bytes), stats and errors as hopm_iterate / hopm_solve
+ * (no refinement stage); lambda = norm of the contraction for x_{d-1}.
+ * No host synchronisation in hopm_jacobi_iterate. */
+int32_t hopm_jacobi_iterate(const tvc_tensor* A, double* x, int32_t sweeps, void* ws,
+                            size_t ws_bytes, hopm_stats* d_stats, void* stream);
+int32_t hopm_jacobi_solve(const tvc_tensor* A, double* x, double tol, int32_t max_sweeps,
+                          int32_t check_every, void* ws, size_t ws_bytes, hopm_stats* h_out,
+                          void* stream);
+
 /* ---------------------------------------------------------------------------
  * Lower-precision storage (Sec. 5.5: values stored narrow, promoted before
  * arithmetic).  Converts a TVC_F32 tensor `src` into `dst_dtype` (TVC_F16,

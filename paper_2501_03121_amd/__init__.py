@@ -13,7 +13,7 @@ _CORE = {
     "contract", "contract_plan", "hopm_iterate", "hopm_solve", "hopm_workspace", "read_stats",
     "quantize", "probe_read", "probe_copy", "pack_vectors", "unpack_vectors", "describe",
     "HopmResult", "backward_x", "backward_A", "leave_one_out", "rank_update",
-    "hopm_iterate_record", "hopm_backward", "quantize",
+    "hopm_iterate_record", "hopm_backward", "hopm_jacobi_iterate", "hopm_jacobi_solve",
 }
 
 

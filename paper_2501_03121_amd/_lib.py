@@ -98,6 +98,10 @@ SIGNATURES = {
                                c_void_p]),
     "hopm_solve": (c_int32, [POINTER(TvcTensor), POINTER(TvcTensor), c_void_p, c_double, c_int32,
                              c_int32, c_int32, c_void_p, c_size_t, POINTER(HopmStats), c_void_p]),
+    "hopm_jacobi_iterate": (c_int32, [POINTER(TvcTensor), c_void_p, c_int32, c_void_p, c_size_t, c_void_p,
+                                      c_void_p]),
+    "hopm_jacobi_solve": (c_int32, [POINTER(TvcTensor), c_void_p, c_double, c_int32, c_int32, c_void_p,
+                                    c_size_t, POINTER(HopmStats), c_void_p]),
     "tvc_quantize": (c_int32, [POINTER(TvcTensor), c_void_p, c_int32, c_void_p, c_int32, c_void_p]),
     "tvc_backward_x_workspace_bytes": (c_size_t, [POINTER(TvcTensor), c_int32]),
     "tvc_backward_x": (c_int32, [POINTER(TvcTensor), c_int32, c_void_p, c_void_p, c_void_p, c_size_t,

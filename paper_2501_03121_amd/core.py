@@ -181,6 +181,53 @@ def hopm_iterate(A: torch.Tensor, x: torch.Tensor, sweeps: int = 1, scale: torch
     return stats
 
 
+def hopm_jacobi_iterate(A: torch.Tensor, x: torch.Tensor, sweeps: int = 1,
+                        scale: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                        stats: torch.Tensor | None = None) -> torch.Tensor:
+    """`sweeps` Jacobi HOPM sweeps (one pass over A each) in place on the
+    packed float64 vectors `x`; returns the device stats record."""
+    desc = describe(A, scale)
+    _require_cuda(x)
+    if x.dtype != torch.float64 or x.numel() != sum(A.shape):
+        raise TypeError("x must be float64 with sum(dims) elements")
+    lib = L.lib()
+    need = lib.hopm_workspace_bytes(desc)
+    if ws is None:
+        ws = _WS.get(need, A.device)
+    if stats is None:
+        stats = torch.zeros(32, dtype=torch.uint8, device=A.device)
+    L.check(lib.hopm_jacobi_iterate(desc, x.data_ptr(), int(sweeps), _WS.ptr(ws), int(need),
+                                    stats.data_ptr(), _stream()))
+    return stats
+
+
+def hopm_jacobi_solve(A: torch.Tensor, x: torch.Tensor, tol: float = 1e-6, max_sweeps: int = 1000,
+                      check_every: int = 1, scale: torch.Tensor | None = None) -> HopmResult:
+    """Jacobi sweeps until delta < tol or max_sweeps (synchronises every
+    check_every sweeps)."""
+    desc = describe(A, scale)
+    _require_cuda(x)
+    lib = L.lib()
+    need = lib.hopm_workspace_bytes(desc)
+    ws = _WS.get(need, A.device)
+    hp = _pinned_stats()
+    st = lib.hopm_jacobi_solve(desc, x.data_ptr(), float(tol), int(max_sweeps), int(check_every),
+                               _WS.ptr(ws), int(need), hp, _stream())
+    h = L.HopmStats.from_buffer_copy(ctypes.string_at(_PINNED_STATS.data_ptr(), ctypes.sizeof(L.HopmStats)))
+    if st not in (L.TVC_OK, L.TVC_ENOTCONVERGED):
+        L.check(st)
+    return HopmResult(h.lam, h.delta, h.sweeps, h.refine_sweeps, st)
+
+
+def _pinned_stats():
+    """The result record in pinned host memory: the library reads each
+    convergence check straight into it."""
+    global _PINNED_STATS
+    if _PINNED_STATS is None:
+        _PINNED_STATS = torch.empty(ctypes.sizeof(L.HopmStats), dtype=torch.uint8, pin_memory=True)
+    return ctypes.cast(_PINNED_STATS.data_ptr(), ctypes.POINTER(L.HopmStats))
+
+
 def read_stats(stats: torch.Tensor) -> HopmResult:
     raw = stats.cpu().numpy().tobytes()
     s = L.HopmStats.from_buffer_copy(raw)
@@ -199,12 +246,7 @@ def hopm_solve(A: torch.Tensor, x: torch.Tensor, tol: float = 1e-6, max_sweeps: 
     lib = L.lib()
     need = lib.hopm_workspace_bytes(desc)
     ws = _WS.get(need, A.device)
-    # the result record in pinned host memory: the library reads each
-    # convergence check straight into it
-    global _PINNED_STATS
-    if _PINNED_STATS is None:
-        _PINNED_STATS = torch.empty(ctypes.sizeof(L.HopmStats), dtype=torch.uint8, pin_memory=True)
-    hp = ctypes.cast(_PINNED_STATS.data_ptr(), ctypes.POINTER(L.HopmStats))
+    hp = _pinned_stats()
     st = lib.hopm_solve(desc, rdesc, x.data_ptr(), float(tol), int(max_sweeps), int(check_every),
                         int(refine_sweeps), _WS.ptr(ws), int(need), hp, _stream())
     h = L.HopmStats.from_buffer_copy(ctypes.string_at(_PINNED_STATS.data_ptr(), ctypes.sizeof(L.HopmStats)))

@@ -1,0 +1,260 @@
+// One pass over A that gives the two contractions a Jacobi HOPM sweep needs
+// from the same vectors.  A is viewed as P rows of R contiguous elements
+// (P = n_0 n_1 and R = n_2 ... n_{d-1} for order d >= 3; P = n_0, R = n_1 for
+// a matrix), with weights w (R values) and u (P values):
+//   m[p] = oscale[p / odiv] * sum_c A[p, c] w[c]      rows against w
+//   z[c] = sum_p u[p] A[p, c]                          columns against u
+// Each element of A is loaded once and used in two FMAs, so the pass is
+// HBM-bound like a single contraction (4 flops per element).
+//
+// Work split: a wave owns a strip of 64 * CPT column units (16-byte vectors,
+// or single elements on the scalar path) of a chunk of consecutive rows.  Its
+// lanes keep the strip's weights and column sums in registers while they
+// stream down the rows (each wave load is 1 KB contiguous); a row's partial
+// dot is summed across the wave and stored per strip.  Several strips add
+// their row partials, several chunks their column partials, in fixed order
+// (k_dual_fin_*), so results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "common.h"
+#include "internal.h"
+
+namespace tvc {
+
+namespace {
+
+constexpr int kDualWaves = 4;            // waves per 256-thread workgroup
+constexpr i64 kDualTargetTasks = 4096;   // strips x chunks aimed at
+constexpr i64 kDualMinRows = 16;         // rows per chunk, at least
+
+template <typename Acc>
+struct DualArgs {
+  const void* A;
+  const Acc* w;        // R weights of the rows
+  const Acc* u;        // P weights of the columns
+  Acc* m;              // P row results (nstrips == 1) or nstrips * P partials
+  Acc* z;              // R column results (nchunks == 1) or nchunks * R partials
+  const float* oscale; // optional row scale (applied when nstrips == 1)
+  i64 odiv;
+  i64 P, R;
+  i64 ucount;          // column units per row
+  i64 nstrips, nchunks, rows_per_chunk;
+};
+
+// A lane's unit i of strip s: unit index, first column it loads (the last
+// unit of a ragged row is moved back to end at the row end), first column it
+// owns.  Lanes past the row end load the last unit and own nothing.
+template <int EU>
+__device__ __forceinline__ void unit_cols(i64 un, i64 ucount, i64 R, i64& cs, i64& own) {
+  if (un < ucount) {
+    own = un * EU;
+    cs = own < R - EU ? own : R - EU;
+  } else {
+    own = R;
+    cs = R - EU;
+  }
+}
+
+template <int DT, bool VEC, int CPT, int RB>
+__global__ __launch_bounds__(kDualWaves * kWave) void k_dual(DualArgs<typename St<DT>::Acc> a) {
+  typedef Unit<DT, VEC> U;
+  typedef typename St<DT>::Acc Acc;
+  constexpr int EU = U::EU;
+  const int lane = lane_id();
+  const i64 wave = (i64)blockIdx.x * kDualWaves + threadIdx.x / kWave;
+  const i64 nwaves = (i64)gridDim.x * kDualWaves;
+  const i64 ntasks = a.nstrips * a.nchunks;
+  for (i64 t = wave; t < ntasks; t += nwaves) {
+    i64 q, s;
+    divmod(t, a.nstrips, q, s);
+    const i64 p0 = q * a.rows_per_chunk;
+    const i64 p1 = p0 + a.rows_per_chunk < a.P ? p0 + a.rows_per_chunk : a.P;
+    i64 cs[CPT], own[CPT];
+    Acc wr[CPT][EU], col[CPT][EU];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const i64 un = s * (kWave * CPT) + (i64)i * kWave + lane;
+      unit_cols<EU>(un, a.ucount, a.R, cs[i], own[i]);
+#pragma unroll
+      for (int e = 0; e < EU; ++e) {
+        wr[i][e] = (cs[i] + e >= own[i]) ? a.w[cs[i] + e] : (Acc)0;
+        col[i][e] = (Acc)0;
+      }
+    }
+    for (i64 pb = p0; pb < p1; pb += RB) {
+      typename U::Raw raw[RB][CPT];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const i64 p = pb + r < p1 ? pb + r : p1 - 1;   // rows past the chunk repeat its last
+        const i64 base = p * a.R;
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) raw[r][i] = U::load(a.A, base + cs[i]);
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        if (pb + r >= p1) break;   // wave-uniform
+        const Acc up = a.u[pb + r];
+        Acc dot = (Acc)0;
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) {
+          Acc v[EU];
+          U::unpack(raw[r][i], v);
+#pragma unroll
+          for (int e = 0; e < EU; ++e) {
+            dot = fma(v[e], wr[i][e], dot);
+            col[i][e] = fma(up, v[e], col[i][e]);
+          }
+        }
+        dot = group_sum(dot, 6);
+        if (lane == 0) {
+          const i64 p = pb + r;
+          if (a.nstrips == 1) {
+            Acc sc = (Acc)1;
+            if (a.oscale) sc = (Acc)a.oscale[p / a.odiv];
+            a.m[p] = dot * sc;
+          } else {
+            a.m[s * a.P + p] = dot;
+          }
+        }
+      }
+    }
+    Acc* zo = a.nchunks == 1 ? a.z : a.z + q * a.R;
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      if (own[i] >= a.R) continue;
+      if constexpr (VEC) {
+        if (cs[i] == own[i]) {
+          store_w<Acc, EU>(zo + cs[i], col[i]);
+          continue;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < EU; ++e)
+        if (cs[i] + e >= own[i]) zo[cs[i] + e] = col[i][e];
+    }
+  }
+}
+
+// m[p] = oscale[p / odiv] * sum_{s < nstrips} part[s * P + p], strips in order
+template <typename Acc>
+__global__ void k_dual_fin_m(const Acc* part, Acc* m, i64 P, i64 nstrips, const float* oscale,
+                             i64 odiv) {
+  for (i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (i64)gridDim.x * blockDim.x) {
+    Acc s = (Acc)0;
+    for (i64 k = 0; k < nstrips; ++k) s += part[k * P + p];
+    if (oscale) s *= (Acc)oscale[p / odiv];
+    m[p] = s;
+  }
+}
+
+// z[c] = sum_{q < nchunks} part[q * R + c], chunks in order
+template <typename Acc>
+__global__ void k_dual_fin_z(const Acc* part, Acc* z, i64 R, i64 nchunks) {
+  for (i64 c = (i64)blockIdx.x * blockDim.x + threadIdx.x; c < R; c += (i64)gridDim.x * blockDim.x) {
+    Acc s = (Acc)0;
+    for (i64 k = 0; k < nchunks; ++k) s += part[k * R + c];
+    z[c] = s;
+  }
+}
+
+template <int DT>
+constexpr int dual_cpt(bool vec) {
+  return !vec ? 4 : (St<DT>::EPV <= 4 ? 4 : (St<DT>::EPV == 8 ? 2 : 1));
+}
+
+template <int DT, bool VEC>
+hipError_t launch_dual(const DualArgs<typename St<DT>::Acc>& a, int grid, hipStream_t st) {
+  constexpr int CPT = dual_cpt<DT>(VEC);
+  constexpr int RB = 8 / CPT;
+  hipLaunchKernelGGL((k_dual<DT, VEC, CPT, RB>), dim3(grid), dim3(kDualWaves * kWave), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int DT>
+hipError_t run_dual_dt(const void* A, i64 P, i64 R, const void* w, const void* u, void* m, void* z,
+                       const float* oscale, i64 odiv, const DualPlan& p, void* part, hipStream_t st) {
+  typedef typename St<DT>::Acc Acc;
+  DualArgs<Acc> a;
+  a.A = A;
+  a.w = (const Acc*)w;
+  a.u = (const Acc*)u;
+  Acc* mp = (Acc*)part;
+  Acc* zp = (Acc*)((char*)part + p.m_part_bytes);
+  a.m = p.nstrips > 1 ? mp : (Acc*)m;
+  a.z = p.nchunks > 1 ? zp : (Acc*)z;
+  a.oscale = oscale;
+  a.odiv = odiv;
+  a.P = P;
+  a.R = R;
+  a.ucount = p.ucount;
+  a.nstrips = p.nstrips;
+  a.nchunks = p.nchunks;
+  a.rows_per_chunk = p.rows_per_chunk;
+  hipError_t e = p.vec ? launch_dual<DT, true>(a, p.grid, st) : launch_dual<DT, false>(a, p.grid, st);
+  if (e != hipSuccess) return e;
+  const int cus = device_cus();
+  if (p.nstrips > 1) {
+    const int g = (int)std::max<i64>(1, std::min<i64>((P + 255) / 256, 4 * (i64)cus));
+    hipLaunchKernelGGL((k_dual_fin_m<Acc>), dim3(g), dim3(256), 0, st, (const Acc*)mp, (Acc*)m, P,
+                       p.nstrips, oscale, odiv);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (p.nchunks > 1) {
+    const int g = (int)std::max<i64>(1, std::min<i64>((R + 255) / 256, 4 * (i64)cus));
+    hipLaunchKernelGGL((k_dual_fin_z<Acc>), dim3(g), dim3(256), 0, st, (const Acc*)zp, (Acc*)z, R,
+                       p.nchunks);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace
+
+DualPlan plan_dual(int dtype, i64 P, i64 R, bool a4) {
+  DualPlan p;
+  const int epv = (int)(16 / elem_bytes(dtype));
+  const size_t eb = elem_bytes(dtype);
+  // 16-byte units need dword-aligned rows at least one unit long
+  p.vec = a4 && R >= epv && ((size_t)R * eb) % 4 == 0;
+  const int eu = p.vec ? epv : 1;
+  int cpt;
+  switch (dtype) {
+    case TVC_F64: cpt = dual_cpt<TVC_F64>(p.vec); break;
+    case TVC_F32: cpt = dual_cpt<TVC_F32>(p.vec); break;
+    case TVC_F16: cpt = dual_cpt<TVC_F16>(p.vec); break;
+    case TVC_BF16: cpt = dual_cpt<TVC_BF16>(p.vec); break;
+    default: cpt = dual_cpt<TVC_F8E4M3>(p.vec); break;
+  }
+  p.ucount = (R + eu - 1) / eu;
+  p.nstrips = (p.ucount + (i64)kWave * cpt - 1) / ((i64)kWave * cpt);
+  const i64 max_chunks = std::max<i64>(1, (P + kDualMinRows - 1) / kDualMinRows);
+  p.nchunks = std::max<i64>(1, std::min<i64>((kDualTargetTasks + p.nstrips - 1) / p.nstrips, max_chunks));
+  p.rows_per_chunk = (P + p.nchunks - 1) / p.nchunks;
+  p.nchunks = (P + p.rows_per_chunk - 1) / p.rows_per_chunk;
+  const size_t ab = acc_bytes(dtype);
+  p.m_part_bytes = p.nstrips > 1 ? align256((size_t)(p.nstrips * P) * ab) : 0;
+  p.z_part_bytes = p.nchunks > 1 ? align256((size_t)(p.nchunks * R) * ab) : 0;
+  p.part_bytes = p.m_part_bytes + p.z_part_bytes;
+  const i64 tasks = p.nstrips * p.nchunks;
+  const i64 cap = (i64)device_cus() * 16 / kDualWaves;   // 16 waves per CU
+  p.grid = (int)std::max<i64>(1, std::min<i64>((tasks + kDualWaves - 1) / kDualWaves, cap));
+  return p;
+}
+
+hipError_t run_dual(int dtype, const void* A, i64 P, i64 R, const void* w, const void* u, void* m,
+                    void* z, const float* oscale, i64 odiv, const DualPlan& p, void* part,
+                    hipStream_t st) {
+  switch (dtype) {
+    case TVC_F64: return run_dual_dt<TVC_F64>(A, P, R, w, u, m, z, oscale, odiv, p, part, st);
+    case TVC_F32: return run_dual_dt<TVC_F32>(A, P, R, w, u, m, z, oscale, odiv, p, part, st);
+    case TVC_F16: return run_dual_dt<TVC_F16>(A, P, R, w, u, m, z, oscale, odiv, p, part, st);
+    case TVC_BF16: return run_dual_dt<TVC_BF16>(A, P, R, w, u, m, z, oscale, odiv, p, part, st);
+    case TVC_F8E4M3: return run_dual_dt<TVC_F8E4M3>(A, P, R, w, u, m, z, oscale, odiv, p, part, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace tvc

@@ -81,20 +81,24 @@ __device__ __forceinline__ double block_sum_1024(double v, double* sh) {
   return s;
 }
 
-enum { kFirstJ = 1, kLastJ = 2 };
+enum { kFirstJ = 1, kLastJ = 2, kAlignSign = 4 };
 
 // x <- y / ||y||, mirrored into wv; delta and lambda bookkeeping in double.
+// kAlignSign (Jacobi sweeps): x <- -y / ||y|| when <y, x> < 0, so the new
+// vector keeps the old one's orientation.
 template <typename Acc>
 __global__ __launch_bounds__(kNormBlock) void k_normalize(const Acc* y, i64 n, double* x, Acc* wv,
                                                           hopm_stats* st, int flags,
                                                           double* norm_out) {
   __shared__ double sh[kNormBlock / kWave];
-  double ss = 0.0;
+  double ss = 0.0, yx = 0.0;
   for (i64 i = threadIdx.x; i < n; i += kNormBlock) {
     const double v = (double)y[i];
     ss += v * v;
+    yx += v * x[i];
   }
   ss = block_sum_1024(ss, sh);
+  if (flags & kAlignSign) yx = block_sum_1024(yx, sh);
   const double nrm = sqrt(ss);
   if (norm_out && threadIdx.x == 0) *norm_out = nrm;
   if (!(nrm > 0.0) || !isfinite(nrm)) {
@@ -108,7 +112,7 @@ __global__ __launch_bounds__(kNormBlock) void k_normalize(const Acc* y, i64 n, d
     }
     return;
   }
-  const double inv = 1.0 / nrm;
+  const double inv = ((flags & kAlignSign) && yx < 0.0) ? -1.0 / nrm : 1.0 / nrm;
   double dd = 0.0;
   for (i64 i = threadIdx.x; i < n; i += kNormBlock) {
     const double v = (double)y[i] * inv;
@@ -358,8 +362,8 @@ struct Layout {
   i64 nsum = 0, nmax = 0, N = 0, R1 = 1, n01 = 1;
   // byte offsets into ws
   size_t o_wv = 0, o_y = 0, o_M = 0, o_w1 = 0, o_w2 = 0, o_Wa = 0, o_Wb = 0, o_Ca = 0, o_Cb = 0,
-         o_stats = 0, o_part = 0;
-  size_t part_bytes = 0;
+         o_stats = 0, o_part = 0, o_Y = 0, o_dpart = 0;
+  size_t part_bytes = 0, dpart_bytes = 0;
   size_t total = 0;
 };
 
@@ -459,6 +463,12 @@ Layout make_layout(const tvc_tensor* A) {
         pb = std::max(pb, plan_tvc((int)t[0], t[1], t[2], t[3], a16, w16).part_bytes);
   Lt.part_bytes = pb;
   Lt.o_part = take(pb);
+  // Jacobi sweeps: the d contraction results, and the one-pass scratch
+  Lt.o_Y = take((size_t)Lt.wsum * ab);
+  const i64 P = Lt.d >= 3 ? Lt.n01 : Lt.n[0];
+  const i64 R = Lt.d >= 3 ? Lt.R1 : (Lt.d == 2 ? Lt.n[1] : 1);
+  Lt.dpart_bytes = std::max(plan_dual(Lt.dt, P, R, true).part_bytes, plan_dual(Lt.dt, P, R, false).part_bytes);
+  Lt.o_dpart = take(Lt.dpart_bytes);
   Lt.total = o;
   return Lt;
 }
@@ -487,9 +497,9 @@ tvc_status run(const Ctx& c, int dt, const void* A, i64 L, i64 M, i64 R, const v
 }
 
 template <typename Acc>
-tvc_status normalize(const Ctx& c, const void* y, int j) {
+tvc_status normalize(const Ctx& c, const void* y, int j, int extra_flags = 0) {
   const Layout& Lt = *c.Lt;
-  int flags = (j == 0 ? kFirstJ : 0) | (j == Lt.d - 1 ? kLastJ : 0);
+  int flags = (j == 0 ? kFirstJ : 0) | (j == Lt.d - 1 ? kLastJ : 0) | extra_flags;
   hipLaunchKernelGGL((k_normalize<Acc>), dim3(1), dim3(kNormBlock), 0, c.s, (const Acc*)y,
                      Lt.n[j], c.x + Lt.off[j], c.at<Acc>(Lt.o_wv) + Lt.woff[j], c.st, flags,
                      c.norms ? c.norms + j : nullptr);
@@ -760,8 +770,83 @@ tvc_status sweep(const Ctx& c) {
   return tl.flush();
 }
 
+// ---------------------------------------------------------------- Jacobi sweep
+// Jacobi HOPM, a variant of the method (the paper's sweep is Gauss-Seidel):
+// every x_j of a sweep is the normalised contraction of A with the vectors
+// of the previous sweep.  All d contractions then come from ONE pass over A
+// (run_dual on the [n_0 n_1][n_2 ... n_{d-1}] view): M = A x_2 .. x_{d-1}
+// gives y_0 = M x_1 and y_1 = M^T x_0, W_2 = A x_0 x_1 gives y_j (j >= 2)
+// contracted with the other previous vectors.  The d results are normalised
+// after all of them exist, each with the sign that keeps <x_j(new),
+// x_j(old)> >= 0 (without it, even orders can flip the signs of all vectors
+// every sweep, and delta would never fall; the directions are the same);
+// lambda = ||y_{d-1}|| and delta as in a Gauss-Seidel sweep.
 template <typename Acc>
-tvc_status iterate(const Ctx& c, int sweeps) {
+tvc_status jacobi_sweep(const Ctx& c) {
+  const Layout& Lt = *c.Lt;
+  const tvc_tensor* A = c.A;
+  const int d = Lt.d;
+  const i64* n = Lt.n;
+  Acc* wv = c.at<Acc>(Lt.o_wv);
+  Acc* Y = c.at<Acc>(Lt.o_Y);
+  const bool f8 = A->dtype == TVC_F8E4M3;
+  const bool a4 = ((uintptr_t)A->data % 4) == 0;
+  const Acc* ysrc[TVC_MAX_ORDER];
+  for (int j = 0; j < d; ++j) ysrc[j] = Y + Lt.woff[j];
+  if (d == 2) {
+    const Acc* u = wv + Lt.woff[0];
+    if (f8) {   // the slab scale of row i0 folded into the column weights
+      Acc* sw = c.at<Acc>(Lt.o_w2);
+      TVC_TRY(kron<Acc>(c, 0, 1, sw, A->slab_scale, 1));
+      u = sw;
+    }
+    const DualPlan p = plan_dual(A->dtype, n[0], n[1], a4);
+    TVC_TRY_HIP(run_dual(A->dtype, A->data, n[0], n[1], wv + Lt.woff[1], u, Y + Lt.woff[0],
+                         Y + Lt.woff[1], f8 ? A->slab_scale : nullptr, 1, p, c.ws + Lt.o_dpart, c.s));
+  } else {
+    const Acc* w1 = wv + Lt.woff[2];
+    if (d >= 4) {
+      Acc* w1b = c.at<Acc>(Lt.o_w1);
+      TVC_TRY(kron<Acc>(c, 2, d, w1b, nullptr, 1));
+      w1 = w1b;
+    }
+    Acc* w2 = c.at<Acc>(Lt.o_w2);
+    TVC_TRY(kron<Acc>(c, 0, 2, w2, f8 ? A->slab_scale : nullptr, n[1]));
+    Acc* Mm = c.at<Acc>(Lt.o_M);
+    Acc* Wa = c.at<Acc>(Lt.o_Wa);
+    const DualPlan p = plan_dual(A->dtype, Lt.n01, Lt.R1, a4);
+    TVC_TRY_HIP(run_dual(A->dtype, A->data, Lt.n01, Lt.R1, w1, w2, Mm, Wa,
+                         f8 ? A->slab_scale : nullptr, n[1], p, c.ws + Lt.o_dpart, c.s));
+    TVC_TRY(run(c, Lt.acc_dt, Mm, n[0], n[1], 1, wv + Lt.woff[1], Y + Lt.woff[0], nullptr, 1));
+    TVC_TRY(run(c, Lt.acc_dt, Mm, 1, n[0], n[1], wv + Lt.woff[0], Y + Lt.woff[1], nullptr, 1));
+    // y_m, m >= 2: W_2 contracted with every previous x_k, k >= 2, k != m,
+    // from the last mode down; the chain's last contraction writes y_m
+    for (int m = 2; m < d; ++m) {
+      const Acc* src = Wa;
+      Acc* bufs[2] = {c.at<Acc>(Lt.o_Ca), c.at<Acc>(Lt.o_Cb)};
+      int bi = 0;
+      const int last = m == 2 ? 3 : 2;   // mode of the chain's last contraction
+      i64 left = Lt.R1, right = 1;
+      for (int k = d - 1; k >= 2; --k) {
+        left /= n[k];
+        if (k == m) {
+          right = n[k];
+          continue;
+        }
+        Acc* dst = k == last ? Y + Lt.woff[m] : bufs[bi];
+        TVC_TRY(run(c, Lt.acc_dt, src, left, n[k], right, wv + Lt.woff[k], dst, nullptr, 1));
+        src = dst;
+        bi ^= 1;
+      }
+      ysrc[m] = src;   // W_2 itself when d = 3
+    }
+  }
+  for (int j = 0; j < d; ++j) TVC_TRY(normalize<Acc>(c, ysrc[j], j, kAlignSign));
+  return TVC_OK;
+}
+
+template <typename Acc>
+tvc_status iterate(const Ctx& c, int sweeps, bool jacobi = false) {
   const Layout& Lt = *c.Lt;
   const int g = (int)std::max<i64>(1, std::min<i64>((Lt.nsum + 255) / 256, 64));
   VecOffsets vo;
@@ -776,7 +861,7 @@ tvc_status iterate(const Ctx& c, int sweeps) {
   TVC_TRY_HIP(hipGetLastError());
   Ctx ci = c;
   for (int i = 0; i < sweeps; ++i) {
-    TVC_TRY(sweep<Acc>(ci));
+    TVC_TRY(jacobi ? jacobi_sweep<Acc>(ci) : sweep<Acc>(ci));
     if (ci.norms) ci.norms += Lt.d;
   }
   return TVC_OK;
@@ -800,15 +885,15 @@ tvc_status check_hopm_args(const tvc_tensor* A, double* x, void* ws, size_t ws_b
 }
 
 tvc_status iterate_any(const tvc_tensor* A, double* x, int sweeps, void* ws, size_t ws_bytes,
-                       hopm_stats* st, hipStream_t s, double* norms = nullptr) {
+                       hopm_stats* st, hipStream_t s, double* norms = nullptr, bool jacobi = false) {
   Layout Lt = make_layout(A);
   TVC_TRY(check_hopm_args(A, x, ws, ws_bytes, Lt));
   if (sweeps < 1) return fail(TVC_EINVAL, "sweeps must be >= 1");
   if (!st) return fail(TVC_EINVAL, "stats pointer is NULL");
   if (norms && (uintptr_t)norms % 8) return fail(TVC_EINVAL, "norms misaligned");
   Ctx c{&Lt, A, x, (char*)ws, st, s, norms};
-  if (A->dtype == TVC_F64) return iterate<double>(c, sweeps);
-  return iterate<float>(c, sweeps);
+  if (A->dtype == TVC_F64) return iterate<double>(c, sweeps, jacobi);
+  return iterate<float>(c, sweeps, jacobi);
 }
 
 // ---------------------------------------------------------------- leave-one-out
@@ -1153,6 +1238,53 @@ int32_t hopm_solve(const tvc_tensor* A, const tvc_tensor* A_refine, double* x, d
     return fail(TVC_ENOTCONVERGED, rdone ? "refine_sweeps reached before delta < tol"
                                           : "max_sweeps reached before delta < tol");
   return TVC_OK;
+}
+
+int32_t hopm_jacobi_iterate(const tvc_tensor* A, double* x, int32_t sweeps, void* ws,
+                            size_t ws_bytes, hopm_stats* d_stats, void* stream) {
+  return iterate_any(A, x, sweeps, ws, ws_bytes, d_stats, (hipStream_t)stream, nullptr, true);
+}
+
+int32_t hopm_jacobi_solve(const tvc_tensor* A, double* x, double tol, int32_t max_sweeps,
+                          int32_t check_every, void* ws, size_t ws_bytes, hopm_stats* h_out,
+                          void* stream) {
+  TVC_TRY(check_tensor(A, "A"));
+  if (A->order < 2) return fail(TVC_EINVAL, "HOPM needs order >= 2");
+  if (!h_out) return fail(TVC_EINVAL, "h_out is NULL");
+  if (max_sweeps < 1 || check_every < 1) return fail(TVC_EINVAL, "max_sweeps and check_every must be >= 1");
+  if (!(tol >= 0.0)) return fail(TVC_EINVAL, "tol must be >= 0");
+  Layout Lt = make_layout(A);
+  if (ws_bytes < Lt.total) return fail(TVC_EWORKSPACE, "HOPM workspace too small");
+  hopm_stats* dst = (hopm_stats*)((char*)ws + Lt.o_stats);
+  hipStream_t s = (hipStream_t)stream;
+  hopm_stats h{};
+  hopm_stats* rb = &h;
+  {
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, h_out) == hipSuccess && at.type == hipMemoryTypeHost) rb = h_out;
+    (void)hipGetLastError();
+  }
+  int done = 0;
+  while (done < max_sweeps) {
+    const int k = std::min(check_every, max_sweeps - done);
+    TVC_TRY(iterate_any(A, x, k, ws, ws_bytes, dst, s, nullptr, true));
+    TVC_TRY_HIP(hipMemcpyAsync(rb, dst, sizeof(h), hipMemcpyDeviceToHost, s));
+    TVC_TRY_HIP(hipStreamSynchronize(s));
+    h = *rb;
+    done += k;
+    h.sweeps = done;
+    h.refine_sweeps = 0;
+    if (h.status != TVC_OK) {
+      *h_out = h;
+      return fail(TVC_EDEGENERATE, "zero-norm vector during HOPM");
+    }
+    if (h.delta < tol) {
+      *h_out = h;
+      return TVC_OK;
+    }
+  }
+  *h_out = h;
+  return fail(TVC_ENOTCONVERGED, "max_sweeps reached before delta < tol");
 }
 
 int32_t hopm_iterate_record(const tvc_tensor* A, double* x, int32_t sweeps, void* ws,

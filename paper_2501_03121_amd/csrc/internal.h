@@ -86,6 +86,24 @@ tvc_status tvc_run_auto(int dtype, const void* A, i64 L, i64 M, i64 R,
                         const float* oscale, i64 odiv, void* ws, size_t ws_bytes,
                         hipStream_t st, int role = kRoleContract);
 
+// One pass over A viewed as P rows of R elements giving both
+//   m[p] = oscale[p / odiv] * sum_c A[p, c] w[c]   and   z[c] = sum_p u[p] A[p, c]
+// (the two contractions of a Jacobi HOPM sweep).  w, u, m, z: accumulation
+// type of `dtype`; part: plan.part_bytes of scratch.
+struct DualPlan {
+  bool vec = false;          // 16-byte units (dword-aligned rows of at least one unit)
+  i64 ucount = 0;            // column units per row
+  i64 nstrips = 1;           // strips of 64 * CPT units (row partials when > 1)
+  i64 nchunks = 1;           // chunks of rows (column partials when > 1)
+  i64 rows_per_chunk = 0;
+  size_t m_part_bytes = 0, z_part_bytes = 0, part_bytes = 0;
+  int grid = 1;
+};
+DualPlan plan_dual(int dtype, i64 P, i64 R, bool a4);
+hipError_t run_dual(int dtype, const void* A, i64 P, i64 R, const void* w, const void* u, void* m,
+                    void* z, const float* oscale, i64 odiv, const DualPlan& p, void* part,
+                    hipStream_t st);
+
 // Round up to 256 bytes (workspace carving).
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
