@@ -90,6 +90,13 @@ def main() -> int:
     ap.add_argument("--calib", action="store_true",
                     help="only run the read/copy probes of known size (counter calibration)")
     ap.add_argument("--no-table1", action="store_true", help="skip the Table 1 leg of the extras")
+    ap.add_argument("--focus", default="",
+                    help="only repeat one operation (for profilers): tvc:FMT:SHAPE:MODE, sweep:FMT:SHAPE, "
+                         "jacobi:FMT:SHAPE or solve:FMT:SHAPE, with FMT in f64/f32/f16/bf16/e4m3 and SHAPE "
+                         "such as 32^6 or 1024^3")
+    ap.add_argument("--reps", type=int, default=20, help="repetitions of --focus")
+    ap.add_argument("--tune", action="append", default=[],
+                    help="FAMILY:BLOCKS_PER_CU:SPLIT_M passed to tvc_set_tuning before anything runs")
     ap.add_argument("--table1", action="store_true",
                     help="only the hypersquare tensors of the paper's Table 1 (orders 2-10, float32): "
                          "contraction in every mode and one HOPM sweep, %% of peak mean and std per order")
@@ -110,6 +117,9 @@ def main() -> int:
     T0 = time.perf_counter()
     dev = torch.device("cuda:0")
     lib = L.lib()
+    for t in args.tune:
+        f, b, m = (int(v) for v in t.split(":"))
+        L.check(lib.tvc_set_tuning(f, b, m))
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
 
@@ -128,6 +138,10 @@ def main() -> int:
 
     if args.table1:
         print(json.dumps({"table1": run_table1(dev)}), flush=True)
+        return 0
+
+    if args.focus:
+        print(json.dumps({"focus": run_focus(args.focus, args.reps, dev)}), flush=True)
         return 0
 
     # ------------------------------------------------------------ inputs
@@ -375,6 +389,51 @@ def run_looped(tensors, shapes, dev, reps=5):
     return {"per_mode": out,
             "native_mean_std": [round(statistics.mean(nat), 1), round(statistics.stdev(nat), 1)],
             "looped_mean_std": [_mean(loo), _std(loo)]}
+
+
+def run_focus(spec, reps, dev):
+    """Repeat one operation `reps` times after two warm-up calls (for
+    rocprofv3 runs): the contraction of one mode, a Gauss-Seidel or Jacobi
+    sweep, or a solve from the warm start; N(0,1) tensors (planted for
+    sweeps and solves) of the named shape, converted to the named format."""
+    import torch
+
+    import paper_2501_03121_amd as tvc
+    from paper_2501_03121_amd import synth
+    parts = spec.split(":")
+    op, fmt, shape = parts[0], parts[1], parts[2]
+    n, d = (int(v) for v in shape.split("^"))
+    dims = (n,) * d
+    A, a = synth.device_planted(dims, 10.0, 0.1, 200, dev, dtype=torch.float64 if fmt == "f64" else None)
+    S = None
+    if fmt not in ("f32", "f64"):
+        A, S = tvc.quantize(A, fmt)
+    torch.cuda.synchronize()
+    if op == "tvc":
+        k = int(parts[3])
+        acc = torch.float64 if fmt == "f64" else torch.float32
+        x = torch.from_numpy(synth.unit_vectors([n], 300 + k)[0]).to(acc).to(dev)
+        y = torch.empty(A.numel() // n, dtype=acc, device=dev)
+        fn = lambda: tvc.contract(A, x, k, out=y, scale=S)   # noqa: E731
+        nbytes = tvc_bytes(dims, k, A.element_size(), acc.itemsize)
+    else:
+        x = tvc.pack_vectors(synth.warm_start(a, 0.9, 400), dev)
+        if op == "sweep":
+            fn = lambda: tvc.hopm_iterate(A, x, 1, scale=S)   # noqa: E731
+            nbytes = sweep_bytes(dims, A.element_size())
+        elif op == "jacobi":
+            fn = lambda: tvc.hopm_jacobi_iterate(A, x, 1, scale=S)   # noqa: E731
+            nbytes = math.prod(dims) * A.element_size() + 8 * sum(dims)
+        else:
+            x0 = x.clone()
+
+            def fn():
+                x.copy_(x0)
+                tvc.hopm_solve(A, x, tol=1e-6, max_sweeps=500, scale=S)
+            nbytes = 0
+    ms = timed_ms(fn, reps, warm=2)
+    return {"spec": spec, "reps": reps, "ms_median": round(ms, 4),
+            "pct_peak": round(100 * nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 1) if nbytes else None}
 
 
 def run_fp64(dev, reps=5):

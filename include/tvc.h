@@ -362,7 +362,10 @@ int32_t hopm_batch_profile(const void* ws, uint64_t* d_out, void* stream);
  * a negative split_m selects the plain kernels: no LDS output window in any
  * family (outputs are stored as each task finishes) and no column strips
  * (family 1 always uses wave groups sharing column tiles).  Values of 0
- * restore the built-in choice.  Process-wide; set it while no
+ * restore the built-in choice.  family 4 selects how the first pass of a
+ * HOPM sweep contracts its rows: blocks_per_cu > 0 always as strips of
+ * columns whose weights stay in registers, < 0 never, 0 the built-in
+ * rule.  Process-wide; set it while no
  * other thread is launching contractions.
  * ------------------------------------------------------------------------- */
 int32_t tvc_set_tuning(int32_t family, int32_t blocks_per_cu, int32_t split_m);

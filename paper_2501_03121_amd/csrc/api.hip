@@ -263,7 +263,11 @@ int32_t tvc_contract_noalloc(const tvc_tensor* A, int32_t mode, const void* x, v
 }
 
 int32_t tvc_set_tuning(int32_t family, int32_t blocks_per_cu, int32_t split_m) {
-  if (family < 0 || family > 3) return fail(TVC_EINVAL, "family outside [0, 3]");
+  if (family == 4) {   // HOPM pass 1 as register-weight strips
+    tuning().strip_rows = blocks_per_cu > 0 ? 1 : (blocks_per_cu < 0 ? -1 : 0);
+    return TVC_OK;
+  }
+  if (family < 0 || family > 3) return fail(TVC_EINVAL, "family outside [0, 4]");
   if (family == kStage) tuning().stage_off = blocks_per_cu < 0;
   if (family == kCol) tuning().win_off = tuning().strips_off = split_m < 0;
   if (split_m > 0 && split_m != 1 && split_m != 2 && split_m != 4)

@@ -13,7 +13,7 @@
 // stream down the rows (each wave load is 1 KB contiguous); a row's partial
 // dot is summed across the wave and stored per strip.  Several strips add
 // their row partials, several chunks their column partials, in fixed order
-// (k_dual_fin_*), so results do not depend on scheduling.
+// (finalize_sums), so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,7 +57,9 @@ __device__ __forceinline__ void unit_cols(i64 un, i64 ucount, i64 R, i64& cs, i6
   }
 }
 
-template <int DT, bool VEC, int CPT, int RB>
+// COLS = false: rows only (m; no column sums), the row contraction of a
+// Gauss-Seidel sweep's first pass with the strip's weights kept in registers.
+template <int DT, bool VEC, int CPT, int RB, bool COLS>
 __global__ __launch_bounds__(kDualWaves * kWave) void k_dual(DualArgs<typename St<DT>::Acc> a) {
   typedef Unit<DT, VEC> U;
   typedef typename St<DT>::Acc Acc;
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(kDualWaves * kWave) void k_dual(DualArgs<typename S
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         if (pb + r >= p1) break;   // wave-uniform
-        const Acc up = a.u[pb + r];
+        const Acc up = COLS ? a.u[pb + r] : (Acc)0;
         Acc dot = (Acc)0;
 #pragma unroll
         for (int i = 0; i < CPT; ++i) {
@@ -104,7 +106,7 @@ __global__ __launch_bounds__(kDualWaves * kWave) void k_dual(DualArgs<typename S
 #pragma unroll
           for (int e = 0; e < EU; ++e) {
             dot = fma(v[e], wr[i][e], dot);
-            col[i][e] = fma(up, v[e], col[i][e]);
+            if constexpr (COLS) col[i][e] = fma(up, v[e], col[i][e]);
           }
         }
         dot = group_sum(dot, 6);
@@ -120,6 +122,7 @@ __global__ __launch_bounds__(kDualWaves * kWave) void k_dual(DualArgs<typename S
         }
       }
     }
+    if constexpr (!COLS) continue;
     Acc* zo = a.nchunks == 1 ? a.z : a.z + q * a.R;
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
@@ -137,26 +140,76 @@ __global__ __launch_bounds__(kDualWaves * kWave) void k_dual(DualArgs<typename S
   }
 }
 
-// m[p] = oscale[p / odiv] * sum_{s < nstrips} part[s * P + p], strips in order
+// Sums of K partial vectors of C values each (part[k * C + c], k < K), in a
+// fixed order: out[c] = scale(c) * sum_k part[k * C + c], where scale(c) =
+// oscale[c / odiv] when oscale is given.  Few partials: one thread per c.
+// Many (more than kFinDirect): pass 1 sums groups of consecutive k into
+// G partials per c (one thread per (c, group), consecutive threads on
+// consecutive c), pass 2 sums the G group results of each c with one wave.
+constexpr i64 kFinDirect = 32;
+constexpr i64 kFinMaxGroups = 512;
+
 template <typename Acc>
-__global__ void k_dual_fin_m(const Acc* part, Acc* m, i64 P, i64 nstrips, const float* oscale,
-                             i64 odiv) {
-  for (i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (i64)gridDim.x * blockDim.x) {
+__global__ void k_fin_direct(const Acc* part, Acc* out, i64 C, i64 K, const float* oscale, i64 odiv) {
+  for (i64 c = (i64)blockIdx.x * blockDim.x + threadIdx.x; c < C; c += (i64)gridDim.x * blockDim.x) {
     Acc s = (Acc)0;
-    for (i64 k = 0; k < nstrips; ++k) s += part[k * P + p];
-    if (oscale) s *= (Acc)oscale[p / odiv];
-    m[p] = s;
+    for (i64 k = 0; k < K; ++k) s += part[k * C + c];
+    if (oscale) s *= (Acc)oscale[c / odiv];
+    out[c] = s;
   }
 }
 
-// z[c] = sum_{q < nchunks} part[q * R + c], chunks in order
 template <typename Acc>
-__global__ void k_dual_fin_z(const Acc* part, Acc* z, i64 R, i64 nchunks) {
-  for (i64 c = (i64)blockIdx.x * blockDim.x + threadIdx.x; c < R; c += (i64)gridDim.x * blockDim.x) {
+__global__ void k_fin_groups(const Acc* part, Acc* tmp, i64 C, i64 K, i64 G) {
+  const i64 per = (K + G - 1) / G;
+  for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < C * G; i += (i64)gridDim.x * blockDim.x) {
+    i64 g, c;
+    divmod(i, C, g, c);
+    const i64 k0 = g * per, k1 = k0 + per < K ? k0 + per : K;
     Acc s = (Acc)0;
-    for (i64 k = 0; k < nchunks; ++k) s += part[k * R + c];
-    z[c] = s;
+    for (i64 k = k0; k < k1; ++k) s += part[k * C + c];
+    tmp[g * C + c] = s;
   }
+}
+
+template <typename Acc>
+__global__ __launch_bounds__(256) void k_fin_waves(const Acc* tmp, Acc* out, i64 C, i64 G,
+                                                   const float* oscale, i64 odiv) {
+  const int lane = lane_id();
+  for (i64 c = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / kWave; c < C;
+       c += (i64)gridDim.x * blockDim.x / kWave) {
+    Acc s = (Acc)0;
+    for (i64 g = lane; g < G; g += kWave) s += tmp[g * C + c];
+    s = group_sum(s, 6);
+    if (lane == 0) {
+      if (oscale) s *= (Acc)oscale[c / odiv];
+      out[c] = s;
+    }
+  }
+}
+
+i64 fin_groups(i64 K) {
+  return K <= kFinDirect ? 0 : std::min<i64>((K + 7) / 8, kFinMaxGroups);
+}
+
+template <typename Acc>
+hipError_t finalize_sums(const Acc* part, Acc* out, i64 C, i64 K, const float* oscale, i64 odiv,
+                         Acc* tmp, hipStream_t st) {
+  const int cus = device_cus();
+  const i64 G = fin_groups(K);
+  if (G == 0) {
+    const int g = (int)std::max<i64>(1, std::min<i64>((C + 255) / 256, 4 * (i64)cus));
+    hipLaunchKernelGGL((k_fin_direct<Acc>), dim3(g), dim3(256), 0, st, part, out, C, K, oscale, odiv);
+    return hipGetLastError();
+  }
+  int g = (int)std::max<i64>(1, std::min<i64>((C * G + 255) / 256, 8 * (i64)cus));
+  hipLaunchKernelGGL((k_fin_groups<Acc>), dim3(g), dim3(256), 0, st, part, tmp, C, K, G);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  g = (int)std::max<i64>(1, std::min<i64>((C + 3) / 4, 8 * (i64)cus));
+  hipLaunchKernelGGL((k_fin_waves<Acc>), dim3(g), dim3(256), 0, st, (const Acc*)tmp, out, C, G, oscale,
+                     odiv);
+  return hipGetLastError();
 }
 
 template <int DT>
@@ -164,11 +217,11 @@ constexpr int dual_cpt(bool vec) {
   return !vec ? 4 : (St<DT>::EPV <= 4 ? 4 : (St<DT>::EPV == 8 ? 2 : 1));
 }
 
-template <int DT, bool VEC>
+template <int DT, bool VEC, bool COLS>
 hipError_t launch_dual(const DualArgs<typename St<DT>::Acc>& a, int grid, hipStream_t st) {
   constexpr int CPT = dual_cpt<DT>(VEC);
   constexpr int RB = 8 / CPT;
-  hipLaunchKernelGGL((k_dual<DT, VEC, CPT, RB>), dim3(grid), dim3(kDualWaves * kWave), 0, st, a);
+  hipLaunchKernelGGL((k_dual<DT, VEC, CPT, RB, COLS>), dim3(grid), dim3(kDualWaves * kWave), 0, st, a);
   return hipGetLastError();
 }
 
@@ -192,29 +245,26 @@ hipError_t run_dual_dt(const void* A, i64 P, i64 R, const void* w, const void* u
   a.nstrips = p.nstrips;
   a.nchunks = p.nchunks;
   a.rows_per_chunk = p.rows_per_chunk;
-  hipError_t e = p.vec ? launch_dual<DT, true>(a, p.grid, st) : launch_dual<DT, false>(a, p.grid, st);
+  hipError_t e;
+  if (p.cols)
+    e = p.vec ? launch_dual<DT, true, true>(a, p.grid, st) : launch_dual<DT, false, true>(a, p.grid, st);
+  else
+    e = p.vec ? launch_dual<DT, true, false>(a, p.grid, st) : launch_dual<DT, false, false>(a, p.grid, st);
   if (e != hipSuccess) return e;
-  const int cus = device_cus();
+  Acc* tmp = (Acc*)((char*)part + p.m_part_bytes + p.z_part_bytes);
   if (p.nstrips > 1) {
-    const int g = (int)std::max<i64>(1, std::min<i64>((P + 255) / 256, 4 * (i64)cus));
-    hipLaunchKernelGGL((k_dual_fin_m<Acc>), dim3(g), dim3(256), 0, st, (const Acc*)mp, (Acc*)m, P,
-                       p.nstrips, oscale, odiv);
-    e = hipGetLastError();
+    e = finalize_sums<Acc>(mp, (Acc*)m, P, p.nstrips, oscale, odiv, tmp, st);
     if (e != hipSuccess) return e;
   }
-  if (p.nchunks > 1) {
-    const int g = (int)std::max<i64>(1, std::min<i64>((R + 255) / 256, 4 * (i64)cus));
-    hipLaunchKernelGGL((k_dual_fin_z<Acc>), dim3(g), dim3(256), 0, st, (const Acc*)zp, (Acc*)z, R,
-                       p.nchunks);
-    e = hipGetLastError();
-  }
+  if (p.cols && p.nchunks > 1) e = finalize_sums<Acc>(zp, (Acc*)z, R, p.nchunks, nullptr, 1, tmp, st);
   return e;
 }
 
 }  // namespace
 
-DualPlan plan_dual(int dtype, i64 P, i64 R, bool a4) {
+DualPlan plan_dual(int dtype, i64 P, i64 R, bool a4, bool cols) {
   DualPlan p;
+  p.cols = cols;
   const int epv = (int)(16 / elem_bytes(dtype));
   const size_t eb = elem_bytes(dtype);
   // 16-byte units need dword-aligned rows at least one unit long
@@ -236,8 +286,11 @@ DualPlan plan_dual(int dtype, i64 P, i64 R, bool a4) {
   p.nchunks = (P + p.rows_per_chunk - 1) / p.rows_per_chunk;
   const size_t ab = acc_bytes(dtype);
   p.m_part_bytes = p.nstrips > 1 ? align256((size_t)(p.nstrips * P) * ab) : 0;
-  p.z_part_bytes = p.nchunks > 1 ? align256((size_t)(p.nchunks * R) * ab) : 0;
-  p.part_bytes = p.m_part_bytes + p.z_part_bytes;
+  p.z_part_bytes = cols && p.nchunks > 1 ? align256((size_t)(p.nchunks * R) * ab) : 0;
+  // group sums of the two finalize passes (run one after the other)
+  const size_t t_bytes = std::max(align256((size_t)(fin_groups(p.nstrips) * P) * ab),
+                                  cols ? align256((size_t)(fin_groups(p.nchunks) * R) * ab) : 0);
+  p.part_bytes = p.m_part_bytes + p.z_part_bytes + t_bytes;
   const i64 tasks = p.nstrips * p.nchunks;
   const i64 cap = (i64)device_cus() * 16 / kDualWaves;   // 16 waves per CU
   p.grid = (int)std::max<i64>(1, std::min<i64>((tasks + kDualWaves - 1) / kDualWaves, cap));

@@ -45,6 +45,7 @@ struct TvcPlan {
 };
 
 struct Tuning {
+  int strip_rows = 0;      // HOPM pass 1 as strips with register weights: 1 on, -1 off, 0 built-in rule
   int blocks_per_cu[4] = {0, 0, 0, 0};
   bool stage_off = false;  // never pick the LDS-staged family
   bool win_off = false;    // never write outputs through an LDS window
@@ -91,6 +92,7 @@ tvc_status tvc_run_auto(int dtype, const void* A, i64 L, i64 M, i64 R,
 // (the two contractions of a Jacobi HOPM sweep).  w, u, m, z: accumulation
 // type of `dtype`; part: plan.part_bytes of scratch.
 struct DualPlan {
+  bool cols = true;          // false: rows only (m), z is not formed
   bool vec = false;          // 16-byte units (dword-aligned rows of at least one unit)
   i64 ucount = 0;            // column units per row
   i64 nstrips = 1;           // strips of 64 * CPT units (row partials when > 1)
@@ -99,7 +101,7 @@ struct DualPlan {
   size_t m_part_bytes = 0, z_part_bytes = 0, part_bytes = 0;
   int grid = 1;
 };
-DualPlan plan_dual(int dtype, i64 P, i64 R, bool a4);
+DualPlan plan_dual(int dtype, i64 P, i64 R, bool a4, bool cols = true);
 hipError_t run_dual(int dtype, const void* A, i64 P, i64 R, const void* w, const void* u, void* m,
                     void* z, const float* oscale, i64 odiv, const DualPlan& p, void* part,
                     hipStream_t st);

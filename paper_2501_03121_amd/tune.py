@@ -18,7 +18,7 @@ import torch
 from . import _lib as L
 from . import core
 
-FAMILY = {"row": 0, "col": 1, "slab": 2, "stage": 3}
+FAMILY = {"row": 0, "col": 1, "slab": 2, "stage": 3, "hopm_strips": 4}
 
 
 def set_tuning(family: str, blocks_per_cu: int = 0, split_m: int = 0) -> None:
