@@ -137,7 +137,7 @@ def main() -> int:
         return 0
 
     if args.table1:
-        print(json.dumps({"table1": run_table1(dev)}), flush=True)
+        print(json.dumps({"table1": run_table1(dev), "table1_f64": run_table1(dev, dtype="f64")}), flush=True)
         return 0
 
     if args.focus:
@@ -402,8 +402,12 @@ def run_focus(spec, reps, dev):
     from paper_2501_03121_amd import synth
     parts = spec.split(":")
     op, fmt, shape = parts[0], parts[1], parts[2]
-    n, d = (int(v) for v in shape.split("^"))
-    dims = (n,) * d
+    if "^" in shape:
+        n, d = (int(v) for v in shape.split("^"))
+        dims = (n,) * d
+    else:
+        dims = tuple(int(v) for v in shape.split("x"))
+    n = dims[0]
     A, a = synth.device_planted(dims, 10.0, 0.1, 200, dev, dtype=torch.float64 if fmt == "f64" else None)
     S = None
     if fmt not in ("f32", "f64"):
@@ -412,8 +416,8 @@ def run_focus(spec, reps, dev):
     if op == "tvc":
         k = int(parts[3])
         acc = torch.float64 if fmt == "f64" else torch.float32
-        x = torch.from_numpy(synth.unit_vectors([n], 300 + k)[0]).to(acc).to(dev)
-        y = torch.empty(A.numel() // n, dtype=acc, device=dev)
+        x = torch.from_numpy(synth.unit_vectors([dims[k]], 300 + k)[0]).to(acc).to(dev)
+        y = torch.empty(A.numel() // dims[k], dtype=acc, device=dev)
         fn = lambda: tvc.contract(A, x, k, out=y, scale=S)   # noqa: E731
         nbytes = tvc_bytes(dims, k, A.element_size(), acc.itemsize)
     else:
@@ -596,6 +600,7 @@ def run_extras(T, Hs, planted, dev, args):
     out["batch"] = run_batch(dev)
     if not args.no_table1:
         out["table1"] = run_table1(dev)
+        out["table1_f64"] = run_table1(dev, dtype="f64")
     return out
 
 
@@ -628,10 +633,10 @@ def _std(v):
     return round(statistics.stdev(v), 1) if len(v) > 1 else None
 
 
-def run_table1(dev, reps: int = 5):
+def run_table1(dev, reps: int = 5, dtype: str = "f32"):
     """The paper's Table 1 hypersquare tensors (dims chosen not to be
-    multiples of the vector length), here in float32 (same element counts,
-    3.3-4.3 GB): %-of-peak of the contraction in every mode, natively and
+    multiples of the vector length), in float32 (3.3-4.3 GB) or in float64,
+    the paper's own precision and sizes (6.6-8.6 GB): %-of-peak of the contraction in every mode, natively and
     as looped rocBLAS matrix-vector products, and of one HOPM sweep (median
     of `reps` timed calls each), with mean and unbiased std over the modes
     (the Table 2 statistic); the canonical HOPM sweep and the one-pass
@@ -642,33 +647,35 @@ def run_table1(dev, reps: int = 5):
     from paper_2501_03121_amd import synth
 
     rb = Rocblas(torch.cuda.current_stream().cuda_stream)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    eb = 8 if dtype == "f64" else 4
     out = {}
     for d, n in TABLE1.items():
         dims = (n,) * d
-        A = synth.device_normal(dims, 40 + d, dev)
+        A = synth.device_normal(dims, 40 + d, dev, dtype=tdt)
         per, loo = [], []
         for k in range(d):
-            x = torch.from_numpy(synth.unit_vectors([n], 50 + k)[0]).float().to(dev)
-            y = torch.empty(A.numel() // n, dtype=torch.float32, device=dev)
+            x = torch.from_numpy(synth.unit_vectors([n], 50 + k)[0]).to(tdt).to(dev)
+            y = torch.empty(A.numel() // n, dtype=tdt, device=dev)
             ms = timed_ms(lambda: tvc.contract(A, x, k, out=y), reps)
-            per.append(100 * tvc_bytes(dims, k, 4) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
+            per.append(100 * tvc_bytes(dims, k, eb, eb) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
             try:
                 ms = timed_ms(lambda: rb.contract(A, x, k, y), reps)
-                loo.append(100 * tvc_bytes(dims, k, 4) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
+                loo.append(100 * tvc_bytes(dims, k, eb, eb) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
             except RuntimeError:
                 loo.append(None)
             del y
         x = tvc.pack_vectors(synth.unit_vectors(dims, 60), dev)
         ms = timed_ms(lambda: tvc.hopm_iterate(A, x, 1), reps)
-        sweep = 100 * sweep_bytes(dims, 4) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS
+        sweep = 100 * sweep_bytes(dims, eb) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS
         jms = timed_ms(lambda: tvc.hopm_jacobi_iterate(A, x, 1), reps)
-        jac = 100 * (math.prod(dims) * 4 + 8 * sum(dims)) / (jms * 1e-3) / 1e9 / PEAK_HBM_GBS
+        jac = 100 * (math.prod(dims) * eb + 8 * sum(dims)) / (jms * 1e-3) / 1e9 / PEAK_HBM_GBS
         # The canonical HOPM sweep of Sec. 3 on the same kernels: x_j is the
         # contraction of A with every other vector, one mode at a time (the
         # last modes first, so mode indices stay valid), then normalised;
         # Gauss-Seidel order.  It streams A d times, against twice for the
         # fused sweep.
-        xs = [torch.from_numpy(v).float().to(dev) for v in synth.unit_vectors(dims, 60)]
+        xs = [torch.from_numpy(v).to(tdt).to(dev) for v in synth.unit_vectors(dims, 60)]
 
         def canonical():
             for j in range(d):

@@ -256,6 +256,14 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
       const i64 uk = lane + (i64)k * kWave;
       if (uk < a.upr) {
         load_w<Acc, EU>(a.w, uk * EU, wv[k]);
+      } else if (uk == a.upr && a.tail > 0) {
+        // the ragged end as one more unit that re-reads the row's last EU
+        // elements, the ones the last full unit covered weighted 0 (only
+        // the preloading path below reads this unit's slot)
+        load_w<Acc, EU>(a.w, a.ld - EU, wv[k]);
+#pragma unroll
+        for (int e = 0; e < EU; ++e)
+          if (e < EU - a.tail) wv[k][e] = (Acc)0;
       } else {
 #pragma unroll
         for (int e = 0; e < EU; ++e) wv[k][e] = (Acc)0;
@@ -263,20 +271,24 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
     }
   }
   const TaskRange tr = wave_tasks<true>(ntasks);
-  // E4M3 rows that are one pass of the wave (weights in registers, no
-  // ragged end): each 16-byte load costs 24 vector instructions, so a wave
-  // loads its next row group before summing the current one (same sums).
-  if constexpr (EU >= 16 && ROLE != kRoleRowWeights) {
-    if (wreg && a.tail == 0) {
+  // E4M3 and float64 rows that are one pass of the wave (weights in
+  // registers; a ragged end is one more unit, if the wave has a slot for
+  // it): a wave loads its next row group before summing the current one
+  // (same sums), so its arithmetic (24 vector instructions per 16-byte E4M3
+  // load) overlaps loads in flight.
+  if constexpr ((EU >= 16 || sizeof(Acc) == 8) && ROLE != kRoleRowWeights) {
+    if (wreg && (a.tail == 0 || a.upr < (i64)kWave * KU)) {
       auto load_group = [&](i64 g, typename U::Raw (&raw)[KU][RB]) {
 #pragma unroll
         for (int k = 0; k < KU; ++k) {
           const i64 uk = lane + (i64)k * kWave;
-          const bool ok = uk < a.upr;
+          const bool full = uk < a.upr;
+          const bool ok = full || (uk == a.upr && a.tail > 0);
+          const i64 eo = full ? uk * EU : a.ld - EU;
 #pragma unroll
           for (int r = 0; r < RB; ++r) {
             const i64 row = g * RB + r;
-            raw[k][r] = (ok && row < a.L) ? U::load(a.A, row * a.ld + uk * EU) : U::zero();
+            raw[k][r] = (ok && row < a.L) ? U::load(a.A, row * a.ld + eo) : U::zero();
           }
         }
       };
@@ -607,26 +619,28 @@ __device__ __forceinline__ void colw_rows(const char* row0, i64 rs, const i64 (&
     }
   };
   int m = 0;
-  // E4M3 spends 24 vector instructions on each 16-byte load, so a wave
-  // would sit on its arithmetic with no loads in flight: there the next
-  // batch's loads are issued before the current batch is summed (same
-  // order of sums).
-  if constexpr (!ROT && EU >= 16) {
+  // The next batch's loads are issued before the current batch is summed
+  // (same order of sums), so a wave's arithmetic overlaps loads in flight:
+  // E4M3 (24 vector instructions per 16-byte load), float64 (32^6 modes
+  // 0-3 58-73 -> 81-86%, 1024^3 modes 0-1 69-72 -> 88%) and float32 on the
+  // rotated rows (32^6 mode 1: 83.5 -> 85%).  float32 and bf16 elsewhere
+  // lose 2-5 points to the registers the second batch takes.
+  if constexpr (EU >= 16 || sizeof(Acc) == 8 || (ROT && EU == 4)) {
     if (M >= RPB) {
       typename U::Raw cur[RPB][CPT];
 #pragma unroll
       for (int q = 0; q < RPB; ++q)
 #pragma unroll
-        for (int j = 0; j < CPT; ++j) cur[q][j] = U::load(row0 + (i64)q * rs, eo[j]);
+        for (int j = 0; j < CPT; ++j) cur[q][j] = U::load(row0 + (i64)rr(q) * rs, eo[j]);
       for (; m + 2 * RPB <= M; m += RPB) {
         typename U::Raw nxt[RPB][CPT];
 #pragma unroll
         for (int q = 0; q < RPB; ++q)
 #pragma unroll
-          for (int j = 0; j < CPT; ++j) nxt[q][j] = U::load(row0 + (i64)(m + RPB + q) * rs, eo[j]);
+          for (int j = 0; j < CPT; ++j) nxt[q][j] = U::load(row0 + (i64)rr(m + RPB + q) * rs, eo[j]);
 #pragma unroll
         for (int q = 0; q < RPB; ++q) {
-          const Acc wk = wl[m + q];
+          const Acc wk = wl[rr(m + q)];
 #pragma unroll
           for (int j = 0; j < CPT; ++j) {
             Acc v[EU];
@@ -642,7 +656,7 @@ __device__ __forceinline__ void colw_rows(const char* row0, i64 rs, const i64 (&
       }
 #pragma unroll
       for (int q = 0; q < RPB; ++q) {
-        const Acc wk = wl[m + q];
+        const Acc wk = wl[rr(m + q)];
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
           Acc v[EU];
@@ -905,6 +919,39 @@ __global__ __launch_bounds__(ColwShape<WV>::kThreads) void k_slabw(ColArgs<typen
 #pragma unroll
     for (int e = 0; e < EU; ++e) acc[e] = (Acc)0;
     int m = 0;
+    // float64: the next UN rows' loads are issued before this batch is
+    // summed, as in the column strips
+    if constexpr (sizeof(Acc) == 8) {
+      if (M >= UN) {
+        typename U::Raw cur[UN];
+#pragma unroll
+        for (int k = 0; k < UN; ++k) cur[k] = U::load(base + (i64)k * rs, 0);
+        for (; m + 2 * UN <= M; m += UN) {
+          typename U::Raw nxt[UN];
+#pragma unroll
+          for (int k = 0; k < UN; ++k) nxt[k] = U::load(base + (i64)(m + UN + k) * rs, 0);
+#pragma unroll
+          for (int k = 0; k < UN; ++k) {
+            Acc v[EU];
+            U::unpack(cur[k], v);
+            const Acc wk = wl[m + k];
+#pragma unroll
+            for (int e = 0; e < EU; ++e) acc[e] = fma(v[e], wk, acc[e]);
+          }
+#pragma unroll
+          for (int k = 0; k < UN; ++k) cur[k] = nxt[k];
+        }
+#pragma unroll
+        for (int k = 0; k < UN; ++k) {
+          Acc v[EU];
+          U::unpack(cur[k], v);
+          const Acc wk = wl[m + k];
+#pragma unroll
+          for (int e = 0; e < EU; ++e) acc[e] = fma(v[e], wk, acc[e]);
+        }
+        m += UN;
+      }
+    }
     for (; m + UN <= M; m += UN) {
       typename U::Raw raw[UN];
 #pragma unroll
@@ -980,7 +1027,7 @@ __global__ __launch_bounds__(kRowswThreads) void k_rowsw(RowArgs<typename St<DT>
   };
   // E4M3 spends 24 vector instructions on each 16-byte load: a wave loads
   // its next round's rows before summing this round's (same sums)
-  constexpr bool PIPE = EU >= 16;
+  constexpr bool PIPE = EU >= 16 || sizeof(Acc) == 8;
   typename U::Raw nxt[PIPE ? UN : 1];
   if constexpr (PIPE) {
     if (tr.begin + wv < tr.end) load_task(tr.begin + wv, nxt);
@@ -1400,6 +1447,10 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
       int rb = 1;
       if (q <= 4) {
         rb = q <= 1 ? 8 : (q <= 2 ? 4 : 2);
+      } else if (dtype == TVC_F64 && q <= 8) {
+        // float64 rows of 5-8 units per lane: one row per wave with its
+        // weights in registers and the next row's loads in flight
+        rb = 1;
       } else {
         rb = (M * (i64)acc_bytes(dtype) > ((i64)8 << 20)) ? 8 : 2;
       }
