@@ -401,6 +401,9 @@ def run_focus(spec, reps, dev):
     import paper_2501_03121_amd as tvc
     from paper_2501_03121_amd import synth
     parts = spec.split(":")
+    if parts[0] == "batch":
+        r = run_batch(dev)
+        return {k: v for k, v in r.items() if k != "autotune"}
     op, fmt, shape = parts[0], parts[1], parts[2]
     if "^" in shape:
         n, d = (int(v) for v in shape.split("^"))

@@ -282,13 +282,16 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
 #pragma unroll
         for (int k = 0; k < KU; ++k) {
           const i64 uk = lane + (i64)k * kWave;
+          // unmasked loads: a slot past the row's units reads its first
+          // unit (weights 0), a row past the end re-reads the last row (not
+          // stored)
           const bool full = uk < a.upr;
           const bool ok = full || (uk == a.upr && a.tail > 0);
-          const i64 eo = full ? uk * EU : a.ld - EU;
+          const i64 eo = full ? uk * EU : (ok ? a.ld - EU : 0);
 #pragma unroll
           for (int r = 0; r < RB; ++r) {
             const i64 row = g * RB + r;
-            raw[k][r] = (ok && row < a.L) ? U::load(a.A, row * a.ld + eo) : U::zero();
+            raw[k][r] = U::load(a.A, (row < a.L ? row : a.L - 1) * a.ld + eo);
           }
         }
       };
@@ -483,8 +486,10 @@ __global__ __launch_bounds__(kBlock) void k_row_short(RowArgs<typename St<DT>::A
     typename U::Raw raw[kShortUnroll];
 #pragma unroll
     for (int k = 0; k < kShortUnroll; ++k) {
+      // unmasked loads (see k_rowsw): inactive lanes read the row's first
+      // unit and rows past the end the last row, with weights 0 or no store
       const i64 row = base + (i64)k * P + rsub;
-      raw[k] = (active && row < a.L) ? U::load(a.A, row * a.ld + eo) : U::zero();
+      raw[k] = U::load(a.A, (row < a.L ? row : a.L - 1) * a.ld + (active ? eo : 0));
     }
 #pragma unroll
     for (int k = 0; k < kShortUnroll; ++k) {
@@ -1009,20 +1014,29 @@ __global__ __launch_bounds__(kRowswThreads) void k_rowsw(RowArgs<typename St<DT>
   const bool active = sub < a.upr || tl;
   const i64 eo = tl ? a.ld - EU : (i64)sub * EU;
   const int from = tl ? EU - a.tail : 0;
+  // Weights in registers; the elements of a ragged end that the last full
+  // unit already covered, and every element of a lane past the row's
+  // units, are weighted 0, so loads need no masks: an inactive lane reads
+  // the row's first unit, a row past the end re-reads the last row, and
+  // neither is stored (A is finite).
   Acc wk[EU];
   if (active) {
     load_w<Acc, EU>(a.w, eo, wk);
+#pragma unroll
+    for (int e = 0; e < EU; ++e)
+      if (e < from) wk[e] = (Acc)0;
   } else {
 #pragma unroll
     for (int e = 0; e < EU; ++e) wk[e] = (Acc)0;
   }
+  const i64 eol = active ? eo : 0;
   const i64 per = (i64)P * UN;
   const TaskRange tr = block_range((a.L + per - 1) / per);
   auto load_task = [&](i64 t, typename U::Raw (&r)[UN]) {
 #pragma unroll
     for (int k = 0; k < UN; ++k) {
       const i64 row = t * per + (i64)k * P + rsub;
-      r[k] = (active && row < a.L) ? U::load(a.A, row * a.ld + eo) : U::zero();
+      r[k] = U::load(a.A, (row < a.L ? row : a.L - 1) * a.ld + eol);
     }
   };
   // E4M3 spends 24 vector instructions on each 16-byte load: a wave loads
@@ -1065,7 +1079,7 @@ __global__ __launch_bounds__(kRowswThreads) void k_rowsw(RowArgs<typename St<DT>
       U::unpack(raw[k], v);
       Acc s_ = (Acc)0;
 #pragma unroll
-      for (int e = 0; e < EU; ++e) s_ = fma(e < from ? (Acc)0 : v[e], wk[e], s_);
+      for (int e = 0; e < EU; ++e) s_ = fma(v[e], wk[e], s_);
       s_ = group_sum(s_, a.glog);
       const i64 row = base + (i64)k * P + rsub;
       if (sub == 0 && row < a.L)
@@ -1376,11 +1390,13 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
   // Other power-of-two slab widths stay with the slab kernel, which is
   // faster there.  Rows (R == 1) of 33-64 units are staged only in
   // float64, where the row kernel's double accumulators limit occupancy;
-  // in the other formats the row kernel is 10-40% faster on them.  A block
-  // of sb slabs must be a multiple of 16 bytes.
+  // in the other formats the row kernel is 10-40% faster on them.  Rows
+  // narrower than one 16-byte vector are staged in every format (the row
+  // kernel would load them one element per lane: E4M3 8^10 mode 9, 8-byte
+  // rows, 8% of peak).  A block of sb slabs must be a multiple of 16 bytes.
   const i64 sbytes = M * R * b;
   const bool pow2 = (nu & (nu - 1)) == 0;
-  const bool small = R == 1 ? (dtype == TVC_F64 && p.vec && nu > 32 && nu <= 64)
+  const bool small = R == 1 ? ((dtype == TVC_F64 && p.vec && nu > 32 && nu <= 64) || (!p.vec && sbytes < 16))
                             : (sbytes <= 4096 && nu <= 32 && (p.tail > 0 || !pow2 || nu <= 2 || !p.vec));
   if (a16 && small && !tuning().stage_off) {
     const i64 q = 16 / gcd_(16, sbytes);

@@ -125,7 +125,8 @@ def test_batch_and_tuning_argument_errors():
     assert plan.queue_slots == 5 * (descs[0].nt1 + descs[0].nt2 + 2)
     assert lib.hopm_batch_run(None, ctypes.byref(plan), 0, 1 << 24, plan.ws_bytes, 1 << 22, None) == L.TVC_EINVAL
     assert lib.hopm_batch_run(1 << 20, ctypes.byref(plan), 0, 1 << 24, plan.ws_bytes - 1, 1 << 22, None) == L.TVC_EWORKSPACE
-    assert lib.tvc_set_tuning(4, 0, 0) == L.TVC_EINVAL
+    assert lib.tvc_set_tuning(5, 0, 0) == L.TVC_EINVAL
+    assert lib.tvc_set_tuning(4, 0, 0) == L.TVC_OK
     assert lib.tvc_set_tuning(1, 0, 3) == L.TVC_EINVAL
     t = tensor((64, 9, 12), dtype=L.TVC_F32)             # small slabs: staged family
     info = (ctypes.c_int32 * 8)()
