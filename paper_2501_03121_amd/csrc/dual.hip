@@ -85,39 +85,107 @@ __global__ __launch_bounds__(kDualWaves * kWave) void k_dual(DualArgs<typename S
         col[i][e] = (Acc)0;
       }
     }
-    for (i64 pb = p0; pb < p1; pb += RB) {
-      typename U::Raw raw[RB][CPT];
+    if constexpr (COLS) {
+      // Both contractions: rows in blocks of 256, row r's dot kept by lane
+      // (r mod 64) in slot r / 64 of the block and the block's results stored
+      // together (coalesced) instead of one 4-byte store per row; the next RB
+      // rows' loads are issued before the current ones are summed (same
+      // sums).  Measured: Jacobi sweep 32^6 0.78 -> 0.76 ms, 1024^3 0.735 ->
+      // 0.72 ms; the rows-only pass of a Gauss-Seidel sweep keeps the plain
+      // loop below (E4M3 32^6 sweep 0.41 against 0.43 ms, 8^10 1.49 against
+      // 1.57 with this one).
+      auto load_rows = [&](i64 pb, typename U::Raw (&raw)[RB][CPT]) {
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const i64 p = pb + r < p1 ? pb + r : p1 - 1;   // rows past the chunk repeat its last
-        const i64 base = p * a.R;
+        for (int r = 0; r < RB; ++r) {
+          const i64 p = pb + r < p1 ? pb + r : p1 - 1;   // rows past the chunk repeat its last
+          const i64 base = p * a.R;
 #pragma unroll
-        for (int i = 0; i < CPT; ++i) raw[r][i] = U::load(a.A, base + cs[i]);
-      }
+          for (int i = 0; i < CPT; ++i) raw[r][i] = U::load(a.A, base + cs[i]);
+        }
+      };
+      typename U::Raw cur[RB][CPT];
+      load_rows(p0, cur);
+      for (i64 blk = p0; blk < p1; blk += 256) {
+        const i64 bend = blk + 256 < p1 ? blk + 256 : p1;
+        Acc keep[4] = {(Acc)0, (Acc)0, (Acc)0, (Acc)0};
+        for (i64 pb = blk; pb < bend; pb += RB) {
+          typename U::Raw nxt[RB][CPT];
+          if (pb + RB < p1) load_rows(pb + RB, nxt);
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        if (pb + r >= p1) break;   // wave-uniform
-        const Acc up = COLS ? a.u[pb + r] : (Acc)0;
-        Acc dot = (Acc)0;
+          for (int r = 0; r < RB; ++r) {
+            if (pb + r >= bend) break;   // wave-uniform
+            const Acc up = COLS ? a.u[pb + r] : (Acc)0;
+            Acc dot = (Acc)0;
 #pragma unroll
-        for (int i = 0; i < CPT; ++i) {
-          Acc v[EU];
-          U::unpack(raw[r][i], v);
+            for (int i = 0; i < CPT; ++i) {
+              Acc v[EU];
+              U::unpack(cur[r][i], v);
 #pragma unroll
-          for (int e = 0; e < EU; ++e) {
-            dot = fma(v[e], wr[i][e], dot);
-            if constexpr (COLS) col[i][e] = fma(up, v[e], col[i][e]);
+              for (int e = 0; e < EU; ++e) {
+                dot = fma(v[e], wr[i][e], dot);
+                if constexpr (COLS) col[i][e] = fma(up, v[e], col[i][e]);
+              }
+            }
+            dot = group_sum(dot, 6);
+            const int rl = (int)(pb + r - blk);
+#pragma unroll
+            for (int sl = 0; sl < 4; ++sl)
+              if (sl == (rl >> 6) && lane == (rl & 63)) keep[sl] = dot;
+          }
+#pragma unroll
+          for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int i = 0; i < CPT; ++i) cur[r][i] = nxt[r][i];
+        }
+#pragma unroll
+        for (int sl = 0; sl < 4; ++sl) {
+          const i64 p = blk + sl * 64 + lane;
+          if (p < bend) {
+            if (a.nstrips == 1) {
+              Acc sc = (Acc)1;
+              if (a.oscale) sc = (Acc)a.oscale[p / a.odiv];
+              a.m[p] = keep[sl] * sc;
+            } else {
+              a.m[s * a.P + p] = keep[sl];
+            }
           }
         }
-        dot = group_sum(dot, 6);
-        if (lane == 0) {
-          const i64 p = pb + r;
-          if (a.nstrips == 1) {
-            Acc sc = (Acc)1;
-            if (a.oscale) sc = (Acc)a.oscale[p / a.odiv];
-            a.m[p] = dot * sc;
-          } else {
-            a.m[s * a.P + p] = dot;
+      }
+    } else {
+      for (i64 pb = p0; pb < p1; pb += RB) {
+        typename U::Raw raw[RB][CPT];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const i64 p = pb + r < p1 ? pb + r : p1 - 1;   // rows past the chunk repeat its last
+          const i64 base = p * a.R;
+#pragma unroll
+          for (int i = 0; i < CPT; ++i) raw[r][i] = U::load(a.A, base + cs[i]);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          if (pb + r >= p1) break;   // wave-uniform
+          const Acc up = COLS ? a.u[pb + r] : (Acc)0;
+          Acc dot = (Acc)0;
+#pragma unroll
+          for (int i = 0; i < CPT; ++i) {
+            Acc v[EU];
+            U::unpack(raw[r][i], v);
+#pragma unroll
+            for (int e = 0; e < EU; ++e) {
+              dot = fma(v[e], wr[i][e], dot);
+              if constexpr (COLS) col[i][e] = fma(up, v[e], col[i][e]);
+            }
+          }
+          dot = group_sum(dot, 6);
+          if (lane == 0) {
+            const i64 p = pb + r;
+            if (a.nstrips == 1) {
+              Acc sc = (Acc)1;
+              if (a.oscale) sc = (Acc)a.oscale[p / a.odiv];
+              a.m[p] = dot * sc;
+            } else {
+              a.m[s * a.P + p] = dot;
+            }
           }
         }
       }
