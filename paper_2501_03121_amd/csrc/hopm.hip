@@ -662,14 +662,16 @@ struct Tail {
 // weights x_2 (x) ... (x) x_{d-1}.  As strips (run_dual without the column
 // sums) each wave keeps the weights of its columns in registers for a whole
 // chunk of rows; the row kernel re-reads them per row group instead.  With
-// rows of 2^20 elements and more (4 MB or more of weights) the strips are
-// faster (measured: 32^6 sweep bf16 0.729 -> 0.702 ms, E4M3 0.491 -> 0.407,
-// float64 3.18 -> 3.10, 8^10 float32 1.53 -> 1.48; float32 32^6 and 10^9
-// unchanged); on shorter rows the row kernel is (175^4: 1.30 against 1.39).
+// rows of 2^17 elements and more (512 KB or more of weights) the strips are
+// faster in the 4-byte and narrower formats (measured: 32^6 sweep bf16 0.729
+// -> 0.702 ms, E4M3 0.491 -> 0.407, 63^5 float32 1.61 -> 1.51, 8^10 1.53 ->
+// 1.48; float32 32^6 and 10^9 unchanged); on shorter rows the row kernel is
+// (175^4: 1.30 against 1.39).  float64 rows, which preload their next step,
+// are faster than the strips (63^5 sweep 2.61 against 3.26 ms).
 bool pass1_strips(const Ctx& c) {
   const int t = tuning().strip_rows;
   if (t != 0) return t > 0;
-  return c.Lt->R1 >= ((i64)1 << 20) && c.Lt->n01 >= 16;
+  return c.A->dtype != TVC_F64 && c.Lt->R1 >= ((i64)1 << 17) && c.Lt->n01 >= 16;
 }
 
 template <typename Acc>

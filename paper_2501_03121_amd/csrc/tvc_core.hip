@@ -375,8 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
     const bool tail_lane = tail_task && lane < RB && row0 + lane < a.L;
     typename U::Raw traw = U::zero();
     if (tail_lane) traw = U::load(a.A, (row0 + lane) * a.ld + a.ld - EU);
-    for (i64 u = u0 + lane; u < u1; u += (i64)kWave * KU) {
-      typename U::Raw raw[KU][RB];
+    auto load_step = [&](i64 u, typename U::Raw (&raw)[KU][RB], Acc (&wk)[KU][EU]) {
 #pragma unroll
       for (int k = 0; k < KU; ++k) {
         const i64 uk = u + (i64)k * kWave;
@@ -389,13 +388,15 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
         }
         if (!wreg) {
           if (ok) {
-            load_w<Acc, EU>(wr, uk * EU, wv[k]);
+            load_w<Acc, EU>(wr, uk * EU, wk[k]);
           } else {
 #pragma unroll
-            for (int e = 0; e < EU; ++e) wv[k][e] = (Acc)0;
+            for (int e = 0; e < EU; ++e) wk[k][e] = (Acc)0;
           }
         }
       }
+    };
+    auto sum_step = [&](const typename U::Raw (&raw)[KU][RB], const Acc (&wk)[KU][EU]) {
 #pragma unroll
       for (int k = 0; k < KU; ++k)
 #pragma unroll
@@ -403,8 +404,46 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
           Acc v[EU];
           U::unpack(raw[k][r], v);
 #pragma unroll
-          for (int e = 0; e < EU; ++e) acc[r][e % NA] = fma(v[e], wv[k][e], acc[r][e % NA]);
+          for (int e = 0; e < EU; ++e) acc[r][e % NA] = fma(v[e], wk[k][e], acc[r][e % NA]);
         }
+    };
+    if constexpr (sizeof(Acc) == 8) {
+      // float64: the next step's loads are issued before this step is
+      // summed (same sums)
+      typename U::Raw cur[KU][RB];
+      Acc wc[KU][EU];
+      if (wreg) {
+#pragma unroll
+        for (int k = 0; k < KU; ++k)
+#pragma unroll
+          for (int e = 0; e < EU; ++e) wc[k][e] = wv[k][e];
+      }
+      if (u0 + lane < u1) load_step(u0 + lane, cur, wc);
+      for (i64 u = u0 + lane; u < u1; u += (i64)kWave * KU) {
+        typename U::Raw nxt[KU][RB];
+        Acc wn[KU][EU];
+        if (wreg) {
+#pragma unroll
+          for (int k = 0; k < KU; ++k)
+#pragma unroll
+            for (int e = 0; e < EU; ++e) wn[k][e] = wv[k][e];
+        }
+        if (u + (i64)kWave * KU < u1) load_step(u + (i64)kWave * KU, nxt, wn);
+        sum_step(cur, wc);
+#pragma unroll
+        for (int k = 0; k < KU; ++k) {
+#pragma unroll
+          for (int r = 0; r < RB; ++r) cur[k][r] = nxt[k][r];
+#pragma unroll
+          for (int e = 0; e < EU; ++e) wc[k][e] = wn[k][e];
+        }
+      }
+    } else {
+      for (i64 u = u0 + lane; u < u1; u += (i64)kWave * KU) {
+        typename U::Raw raw[KU][RB];
+        load_step(u, raw, wv);
+        sum_step(raw, wv);
+      }
     }
     if (tail_lane) {
       const int from = EU - a.tail;
@@ -546,22 +585,58 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a)
     Acc acc[EU];
 #pragma unroll
     for (int e = 0; e < EU; ++e) acc[e] = (Acc)0;
-    for (i64 m = m0 + grp; m < m1; m += (i64)SPLITM * UN) {
-      typename U::Raw raw[UN];
-      Acc wv[UN];
+    if constexpr (sizeof(Acc) == 8) {
+      // float64: the next UN rows' loads are issued before this batch is
+      // summed (same sums); loads are unmasked (a row past the split reads
+      // the split's last row with weight 0, an inactive lane the slab's
+      // first unit, not stored)
+      auto load_batch = [&](i64 m, typename U::Raw (&raw)[UN], Acc (&wv)[UN]) {
 #pragma unroll
-      for (int k = 0; k < UN; ++k) {
-        const i64 mk = m + (i64)k * SPLITM;
-        const bool ok = mk < m1;
-        raw[k] = (active && ok) ? U::load(a.A, (slab + mk) * a.R + eo) : U::zero();
-        wv[k] = ok ? a.w[mk] : (Acc)0;
+        for (int k = 0; k < UN; ++k) {
+          const i64 mk = m + (i64)k * SPLITM;
+          const bool ok = mk < m1;
+          raw[k] = U::load(a.A, (slab + (ok ? mk : m1 - 1)) * a.R + (active ? eo : 0));
+          wv[k] = ok ? a.w[mk] : (Acc)0;
+        }
+      };
+      typename U::Raw cur[UN];
+      Acc wc[UN];
+      if (m0 + grp < m1) load_batch(m0 + grp, cur, wc);
+      for (i64 m = m0 + grp; m < m1; m += (i64)SPLITM * UN) {
+        typename U::Raw nxt[UN];
+        Acc wn[UN];
+        if (m + (i64)SPLITM * UN < m1) load_batch(m + (i64)SPLITM * UN, nxt, wn);
+#pragma unroll
+        for (int k = 0; k < UN; ++k) {
+          Acc v[EU];
+          U::unpack(cur[k], v);
+#pragma unroll
+          for (int e = 0; e < EU; ++e) acc[e] = fma(v[e], wc[k], acc[e]);
+        }
+#pragma unroll
+        for (int k = 0; k < UN; ++k) {
+          cur[k] = nxt[k];
+          wc[k] = wn[k];
+        }
       }
+    } else {
+      for (i64 m = m0 + grp; m < m1; m += (i64)SPLITM * UN) {
+        typename U::Raw raw[UN];
+        Acc wv[UN];
 #pragma unroll
-      for (int k = 0; k < UN; ++k) {
-        Acc v[EU];
-        U::unpack(raw[k], v);
+        for (int k = 0; k < UN; ++k) {
+          const i64 mk = m + (i64)k * SPLITM;
+          const bool ok = mk < m1;
+          raw[k] = (active && ok) ? U::load(a.A, (slab + mk) * a.R + eo) : U::zero();
+          wv[k] = ok ? a.w[mk] : (Acc)0;
+        }
 #pragma unroll
-        for (int e = 0; e < EU; ++e) acc[e] = fma(v[e], wv[k], acc[e]);
+        for (int k = 0; k < UN; ++k) {
+          Acc v[EU];
+          U::unpack(raw[k], v);
+#pragma unroll
+          for (int e = 0; e < EU; ++e) acc[e] = fma(v[e], wv[k], acc[e]);
+        }
       }
     }
     if constexpr (SPLITM > 1) {
