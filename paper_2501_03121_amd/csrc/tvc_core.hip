@@ -407,9 +407,9 @@ __global__ __launch_bounds__(kBlock) void k_row_long(RowArgs<typename St<DT>::Ac
           for (int e = 0; e < EU; ++e) acc[r][e % NA] = fma(v[e], wk[k][e], acc[r][e % NA]);
         }
     };
-    if constexpr (sizeof(Acc) == 8) {
-      // float64: the next step's loads are issued before this step is
-      // summed (same sums)
+    if constexpr (sizeof(Acc) == 8 || !VEC) {
+      // float64 and one-element units: the next step's loads are issued
+      // before this step is summed (same sums)
       typename U::Raw cur[KU][RB];
       Acc wc[KU][EU];
       if (wreg) {
@@ -585,11 +585,14 @@ __global__ __launch_bounds__(kBlock) void k_col(ColArgs<typename St<DT>::Acc> a)
     Acc acc[EU];
 #pragma unroll
     for (int e = 0; e < EU; ++e) acc[e] = (Acc)0;
-    if constexpr (sizeof(Acc) == 8) {
-      // float64: the next UN rows' loads are issued before this batch is
-      // summed (same sums); loads are unmasked (a row past the split reads
-      // the split's last row with weight 0, an inactive lane the slab's
-      // first unit, not stored)
+    if constexpr (sizeof(Acc) == 8 || !VEC) {
+      // float64 and one-element units: the next UN rows' loads are issued
+      // before this batch is summed (same sums); loads are unmasked (a row
+      // past the split reads the split's last row with weight 0, an
+      // inactive lane the slab's first unit, not stored).  Measured: float64
+      // 30623^2 mode 0 51 -> 75%, bf16 (rows of an odd number of elements,
+      // so one element per load) 9.5 -> 25%; float32 and 16-byte bf16 units
+      // gain nothing or lose (bf16 1024^3 sweep 76 -> 69%).
       auto load_batch = [&](i64 m, typename U::Raw (&raw)[UN], Acc (&wv)[UN]) {
 #pragma unroll
         for (int k = 0; k < UN; ++k) {
