@@ -1238,6 +1238,16 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<typename St<DT>::Acc> a)
   const i64 E = a.M * a.R;
   const int G = 1 << a.glog;
   const int sub = tid & (G - 1);
+  // Within a block every index fits 32 bits (a block is at most the staging
+  // buffer).  Output group o of a block is (slab ls, group rv) = o / Rv,
+  // o % Rv; a thread steps o by S, so (ls, rv) advance by (S / Rv, S % Rv)
+  // with one carry instead of a division per output.
+  const int Rv = (int)(a.R / VE);  // output groups per slab row
+  const int Ei = (int)E, Ri = (int)a.R, Mi = (int)a.M, dE = G * Ri;
+  const int tot = (int)a.sb * Rv;
+  const int S = NT >> a.glog;
+  const int Sq = S / Rv, Sr = S % Rv;
+  const int o0 = tid >> a.glog, ls0 = o0 / Rv, rv0 = o0 % Rv;
   uint4 r[PER];
   i64 nvec = 0;
   auto issue = [&](i64 b) {
@@ -1285,19 +1295,17 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<typename St<DT>::Acc> a)
       }
       wend = ye;
     }
-    const i64 Rv = a.R / VE;          // output groups per slab row
-    const i64 nout = ns * Rv;
+    const int nout = (int)ns * Rv;
     const T* sl = (const T*)lds;
-    for (i64 o = tid >> a.glog; o < a.sb * Rv; o += NT >> a.glog) {
-      Acc acc0[VE], acc1[VE];
+    int ls = ls0, rv = rv0;
+    for (int o = o0; o < tot; o += S) {
+      Acc acc[4][VE];
 #pragma unroll
-      for (int v = 0; v < VE; ++v) acc0[v] = acc1[v] = (Acc)0;
-      i64 ls, rv;
-      divmod(o, Rv, ls, rv);
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < VE; ++v) acc[j][v] = (Acc)0;
       if (o < nout) {
-        const i64 base = ls * E + rv * VE;
-        auto step = [&](i64 m, Acc* acc) {
-          const i64 e = base + m * a.R;
+        auto step = [&](int e, int m, Acc* ac) {
           Acc val[VE];
           if constexpr (VB == 16) {
             unpack16<DT>(*(const uint4*)(sl + e), val);
@@ -1308,25 +1316,34 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<typename St<DT>::Acc> a)
           }
           const Acc wm = wl[m];
 #pragma unroll
-          for (int v = 0; v < VE; ++v) acc[v] = fma(val[v], wm, acc[v]);
+          for (int v = 0; v < VE; ++v) ac[v] = fma(val[v], wm, ac[v]);
         };
-        i64 m = sub;
-        for (; m + G < a.M; m += 2 * G) {
-          step(m, acc0);
-          step(m + G, acc1);
+        int m = sub;
+        int e = ls * Ei + rv * VE + sub * Ri;
+        for (; m + 3 * G < Mi; m += 4 * G, e += 4 * dE) {
+          step(e, m, acc[0]);
+          step(e + dE, m + G, acc[1]);
+          step(e + 2 * dE, m + 2 * G, acc[2]);
+          step(e + 3 * dE, m + 3 * G, acc[3]);
         }
-        if (m < a.M) step(m, acc0);
+        for (; m < Mi; m += G, e += dE) step(e, m, acc[0]);
       }
 #pragma unroll
       for (int v = 0; v < VE; ++v) {
-        Acc t = acc0[v] + acc1[v];
+        Acc t = (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
         for (int off = G >> 1; off >= 1; off >>= 1) t += shfl_xor(t, off);
         if (sub == 0 && o < nout) {
-          const i64 idx = l0 * a.R + o * VE + v;
+          const i64 idx = l0 * a.R + (i64)o * VE + v;
           const Acc out = epilogue(t, a.y, idx, l0 + ls, a.alpha, a.beta, a.oscale, a.odiv);
           if constexpr (WIN) win[idx - org] = out;
           else a.y[idx] = out;
         }
+      }
+      ls += Sq;
+      rv += Sr;
+      if (rv >= Rv) {
+        rv -= Rv;
+        ++ls;
       }
     }
   }
