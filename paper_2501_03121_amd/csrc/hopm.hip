@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <array>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -81,7 +82,10 @@ __device__ __forceinline__ double block_sum_1024(double v, double* sh) {
   return s;
 }
 
-enum { kFirstJ = 1, kLastJ = 2, kAlignSign = 4 };
+// kNoMirror (small-step programs of Jacobi sweeps): update x but not its
+// accumulation-type mirror, which the sweep's remaining contractions still
+// read as the previous vectors; a final mirror step copies x over.
+enum { kFirstJ = 1, kLastJ = 2, kAlignSign = 4, kNoMirror = 8 };
 
 // x <- y / ||y||, mirrored into wv; delta and lambda bookkeeping in double.
 // kAlignSign (Jacobi sweeps): x <- -y / ||y|| when <y, x> < 0, so the new
@@ -205,33 +209,37 @@ __global__ __launch_bounds__(256) void k_kron_chunked(const double* x, KronArgs 
 // workgroup runs instead of one launch per step: contract the last or the
 // first mode of a buffer with a vector mirror, normalise into x_j with the
 // sweep's bookkeeping (as k_normalize), and form the pass-2 weights
-// x_0 (x) x_1.  Buffers 0..2 are LDS (kTailElems values each), the others
+// x_0 (x) x_1, or copy every x into its mirror (the end of a Jacobi
+// sweep).  Buffers 0..2 are LDS (kTailElems values each), the others
 // global.
 // Steps are separated by workgroup barriers, so a step sees the vectors the
 // previous normalisations wrote.
 constexpr int kTailThreads = 512;
 constexpr int kTailElems = 2048;
-constexpr int kTailMaxSteps = 24;
+constexpr int kTailMaxSteps = 48;
 constexpr int kTailLds = 3;
-enum TailOp { kTLast = 0, kTFirst = 1, kTNorm = 2, kTKron = 3, kTCopy = 4 };
+constexpr int kTailGlobal = 12;
+enum TailOp { kTLast = 0, kTFirst = 1, kTNorm = 2, kTKron = 3, kTCopy = 4, kTMirror = 5 };
 
 struct TailStep {
   int op, src, dst, mode, flags;
   i64 a, b;   // kTLast: rows, n; kTFirst: n, rest; kTNorm: n; kTKron: n0, n1; kTCopy: n
 };
+static_assert(kTailMaxSteps * sizeof(TailStep) + 1024 < 4096, "small-step program exceeds the kernel argument space");
 
 template <typename Acc>
 struct TailProg {
   int nsteps;
   TailStep st[kTailMaxSteps];
-  Acc* g[6];                 // global buffers kTailLds ...
+  Acc* g[kTailGlobal];       // global buffers kTailLds ...
   double* x;
   Acc* wv;
   hopm_stats* stats;
   double* norms;             // optional: ||y|| of step j written to norms[j]
   const float* scale0;       // kTKron: optional per-row scale (E4M3 slabs)
   i64 sdiv;
-  i64 off[TVC_MAX_ORDER], woff[TVC_MAX_ORDER];
+  int d;
+  i64 n[TVC_MAX_ORDER], off[TVC_MAX_ORDER], woff[TVC_MAX_ORDER];
 };
 
 template <typename Acc>
@@ -288,12 +296,14 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailProg<Acc> p) {
       const int j = q.mode;
       double* x = p.x + p.off[j];
       Acc* wj = p.wv + p.woff[j];
-      double ss = 0.0;
+      double ss = 0.0, yx = 0.0;
       for (i64 i = tid; i < n; i += kTailThreads) {
         const double v = (double)in[i];
         ss += v * v;
+        yx += v * x[i];
       }
       ss = tail_block_sum<Acc>(ss, sh);
+      if (q.flags & kAlignSign) yx = tail_block_sum<Acc>(yx, sh);
       const double nrm = sqrt(ss);
       if (p.norms && tid == 0) p.norms[j] = nrm;
       if (!(nrm > 0.0) || !isfinite(nrm)) {
@@ -306,14 +316,14 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailProg<Acc> p) {
           }
         }
       } else {
-        const double inv = 1.0 / nrm;
+        const double inv = ((q.flags & kAlignSign) && yx < 0.0) ? -1.0 / nrm : 1.0 / nrm;
         double dd = 0.0;
         for (i64 i = tid; i < n; i += kTailThreads) {
           const double v = (double)in[i] * inv;
           const double df = v - x[i];
           dd += df * df;
           x[i] = v;
-          wj[i] = (Acc)v;
+          if (!(q.flags & kNoMirror)) wj[i] = (Acc)v;
         }
         dd = tail_block_sum<Acc>(dd, sh);
         if (tid == 0) {
@@ -327,6 +337,9 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailProg<Acc> p) {
       }
     } else if (q.op == kTCopy) {
       for (i64 i = tid; i < q.a; i += kTailThreads) out[i] = in[i];
+    } else if (q.op == kTMirror) {
+      for (int j = 0; j < p.d; ++j)
+        for (i64 i = tid; i < p.n[j]; i += kTailThreads) p.wv[p.woff[j] + i] = (Acc)p.x[p.off[j] + i];
     } else {  // kTKron: out[r] = x_0[r / n1] * x_1[r mod n1] (* scale0[r / sdiv])
       const i64 n0 = q.a, n1 = q.b;
       const double* x0 = p.x + p.off[0];
@@ -362,7 +375,7 @@ struct Layout {
   i64 nsum = 0, nmax = 0, N = 0, R1 = 1, n01 = 1;
   // byte offsets into ws
   size_t o_wv = 0, o_y = 0, o_M = 0, o_w1 = 0, o_w2 = 0, o_Wa = 0, o_Wb = 0, o_Ca = 0, o_Cb = 0,
-         o_stats = 0, o_part = 0, o_Y = 0, o_dpart = 0;
+         o_stats = 0, o_part = 0, o_Y = 0, o_J = 0, o_dpart = 0;
   size_t part_bytes = 0, dpart_bytes = 0;
   size_t total = 0;
 };
@@ -393,20 +406,37 @@ void sweep_tvcs(const Layout& Lt, std::vector<std::array<i64, 4>>& out) {
       t /= n[m];
     }
   }
-  // leave-one-out chains on W_2 = A x_0 x_0 x_1 x_1 (modes 2..d-1 kept), each
-  // contracting modes k = d-1 .. 2 except the kept mode m
-  for (int m = 2; m < d; ++m) {
-    i64 left = Lt.R1, right = 1;   // left: modes before k still present
-    for (int k = d - 1; k >= 2; --k) {
-      if (k == m) {
-        left /= n[k];
-        right = n[k];
-        continue;
-      }
-      left /= n[k];
-      out.push_back({Lt.acc_dt, left, n[k], right});
-    }
-  }
+}
+
+// Inputs in global memory up to this many values are read by the single
+// workgroup of a small-step program (about 32 KB in float32: a few
+// microseconds); larger ones get a full launch.
+constexpr i64 kTailIn = 8192;
+
+// Jacobi sweeps take the leave-one-out vectors of W = A x_0 x_0 x_1 x_1
+// (modes 2..d-1 kept) by halving: a node holding modes [a, b) of more than
+// kTailIn values is read once as the matrix [modes a..a+s)][modes a+s..b),
+// s = (b - a) / 2, giving its contractions over the second half (the
+// first-half node) and over the first half (the second-half node); nodes
+// of at most kTailIn values go to the small-step program.  Every node's
+// two outputs get their own stretch of the split buffer (a pending
+// small-step program may still read an earlier one), taken in the order the
+// sweep visits the nodes.  f(a, s, b, P, Q, mo, zo) per split: P x Q the
+// matrix, mo / zo the value offsets of its outputs.
+inline i64 split_pad(i64 v) { return (v + 63) / 64 * 64; }
+
+template <typename F>
+void jacobi_splits(const i64* n, int a, int b, i64 size, i64& top, F&& f) {
+  if (b - a <= 1 || size <= kTailIn) return;
+  const int s = (b - a) / 2;
+  i64 P = 1;
+  for (int k = a; k < a + s; ++k) P *= n[k];
+  const i64 Q = size / P;
+  const i64 mo = top, zo = top + split_pad(P);
+  top = zo + split_pad(Q);
+  f(a, s, b, P, Q, mo, zo);
+  jacobi_splits(n, a, a + s, P, top, f);
+  jacobi_splits(n, a + s, b, Q, top, f);
 }
 
 Layout make_layout(const tvc_tensor* A) {
@@ -463,8 +493,16 @@ Layout make_layout(const tvc_tensor* A) {
         pb = std::max(pb, plan_tvc((int)t[0], t[1], t[2], t[3], a16, w16).part_bytes);
   Lt.part_bytes = pb;
   Lt.o_part = take(pb);
-  // Jacobi sweeps: the d contraction results, and the one-pass scratch
+  // Jacobi sweeps: the d contraction results, the outputs of the halving
+  // of W, and the one-pass scratch
   Lt.o_Y = take((size_t)Lt.wsum * ab);
+  i64 jtop = 0;
+  size_t jpart = 0;
+  if (Lt.d >= 4)
+    jacobi_splits(Lt.n, 2, Lt.d, Lt.R1, jtop, [&](int, int, int, i64 P, i64 Q, i64, i64) {
+      for (int a4 = 0; a4 < 2; ++a4) jpart = std::max(jpart, plan_dual(Lt.acc_dt, P, Q, a4).part_bytes);
+    });
+  Lt.o_J = take((size_t)jtop * ab);
   const i64 P = Lt.d >= 3 ? Lt.n01 : Lt.n[0];
   const i64 R = Lt.d >= 3 ? Lt.R1 : (Lt.d == 2 ? Lt.n[1] : 1);
   // the one-pass scratch also serves pass 1 as strips (rows only)
@@ -472,6 +510,7 @@ Layout make_layout(const tvc_tensor* A) {
   for (int a4 = 0; a4 < 2; ++a4)
     for (int cols = 0; cols < 2; ++cols)
       Lt.dpart_bytes = std::max(Lt.dpart_bytes, plan_dual(Lt.dt, P, R, a4, cols).part_bytes);
+  Lt.dpart_bytes = std::max(Lt.dpart_bytes, jpart);
   Lt.o_dpart = take(Lt.dpart_bytes);
   Lt.total = o;
   return Lt;
@@ -545,11 +584,6 @@ tvc_status kron(const Ctx& c, int m0, int m1, Acc* w, const float* scale0, i64 s
     if (s_ != TVC_OK) return s_;      \
   } while (0)
 
-// Inputs in global memory up to this many values are read by the single
-// workgroup of a small-step program (about 32 KB in float32: a few
-// microseconds); larger ones get a full launch.
-constexpr i64 kTailIn = 8192;
-
 // A buffer of a small-step program: LDS slot 0..2 or a global pointer.
 template <typename Acc>
 struct TBufT {
@@ -587,7 +621,9 @@ struct Tail {
     p.stats = c.st;
     p.norms = c.norms;
     p.sdiv = 1;
+    p.d = Lt.d;
     for (int m = 0; m < Lt.d; ++m) {
+      p.n[m] = Lt.n[m];
       p.off[m] = Lt.off[m];
       p.woff[m] = Lt.woff[m];
     }
@@ -642,11 +678,12 @@ struct Tail {
   tvc_status first(const TBuf& src, i64 n, i64 rest, int mode, const TBuf& dst) {
     return add(kTFirst, &src, &dst, mode, 0, n, rest);
   }
-  tvc_status norm(const TBuf& src, int j) {
+  tvc_status norm(const TBuf& src, int j, int extra_flags = 0) {
     const Layout& Lt = *c.Lt;
-    const int flags = (j == 0 ? kFirstJ : 0) | (j == Lt.d - 1 ? kLastJ : 0);
+    const int flags = (j == 0 ? kFirstJ : 0) | (j == Lt.d - 1 ? kLastJ : 0) | extra_flags;
     return add(kTNorm, &src, nullptr, j, flags, Lt.n[j], 0);
   }
+  tvc_status mirror() { return add(kTMirror, nullptr, nullptr, 0, 0, 0, 0); }
   tvc_status copy(const TBuf& src, const TBuf& dst) {
     return add(kTCopy, &src, &dst, 0, 0, src.size, 0);
   }
@@ -802,11 +839,14 @@ tvc_status sweep(const Ctx& c) {
 // of the previous sweep.  All d contractions then come from ONE pass over A
 // (run_dual on the [n_0 n_1][n_2 ... n_{d-1}] view): M = A x_2 .. x_{d-1}
 // gives y_0 = M x_1 and y_1 = M^T x_0, W_2 = A x_0 x_1 gives y_j (j >= 2)
-// contracted with the other previous vectors.  The d results are normalised
-// after all of them exist, each with the sign that keeps <x_j(new),
-// x_j(old)> >= 0 (without it, even orders can flip the signs of all vectors
-// every sweep, and delta would never fall; the directions are the same);
-// lambda = ||y_{d-1}|| and delta as in a Gauss-Seidel sweep.
+// contracted with the other previous vectors (W halved into one-pass reads
+// down to small-step programs, see jacobi_splits).  Each result is
+// normalised with the sign that keeps <x_j(new), x_j(old)> >= 0 (without
+// it, even orders can flip the signs of all vectors every sweep, and delta
+// would never fall; the directions are the same), into x only: the
+// contractions read the previous vectors from the mirror, which the sweep's
+// last step refreshes.  lambda = ||y_{d-1}|| and delta as in a
+// Gauss-Seidel sweep.
 template <typename Acc>
 tvc_status jacobi_sweep(const Ctx& c) {
   const Layout& Lt = *c.Lt;
@@ -829,46 +869,99 @@ tvc_status jacobi_sweep(const Ctx& c) {
     const DualPlan p = plan_dual(A->dtype, n[0], n[1], a4);
     TVC_TRY_HIP(run_dual(A->dtype, A->data, n[0], n[1], wv + Lt.woff[1], u, Y + Lt.woff[0],
                          Y + Lt.woff[1], f8 ? A->slab_scale : nullptr, 1, p, c.ws + Lt.o_dpart, c.s));
+    for (int j = 0; j < d; ++j) TVC_TRY(normalize<Acc>(c, ysrc[j], j, kAlignSign));
+    return TVC_OK;
+  }
+  typedef TBufT<Acc> TBuf;
+  const Acc* w1 = wv + Lt.woff[2];
+  if (d >= 4) {
+    Acc* w1b = c.at<Acc>(Lt.o_w1);
+    TVC_TRY(kron<Acc>(c, 2, d, w1b, nullptr, 1));
+    w1 = w1b;
+  }
+  Acc* w2 = c.at<Acc>(Lt.o_w2);
+  TVC_TRY(kron<Acc>(c, 0, 2, w2, f8 ? A->slab_scale : nullptr, n[1]));
+  Acc* Mm = c.at<Acc>(Lt.o_M);
+  Acc* Wa = c.at<Acc>(Lt.o_Wa);
+  const DualPlan p = plan_dual(A->dtype, Lt.n01, Lt.R1, a4);
+  TVC_TRY_HIP(run_dual(A->dtype, A->data, Lt.n01, Lt.R1, w1, w2, Mm, Wa,
+                       f8 ? A->slab_scale : nullptr, n[1], p, c.ws + Lt.o_dpart, c.s));
+  // Every x_j is normalised as soon as its contraction exists, with the
+  // mirror left alone (the remaining contractions read the previous
+  // vectors from it) and copied over by the program's last step.
+  constexpr int kJ = kAlignSign | kNoMirror;
+  Tail<Acc> tl(c);
+  if (Lt.n01 <= kTailIn && n[0] <= kTailElems && n[1] <= kTailElems) {
+    const TBuf m = TBuf::global(Mm, Lt.n01), l0 = TBuf::lds(0, n[0]), l1 = TBuf::lds(1, n[1]);
+    TVC_TRY(tl.last(m, n[0], n[1], 1, l0));
+    TVC_TRY(tl.norm(l0, 0, kJ));
+    TVC_TRY(tl.first(m, n[0], n[1], 0, l1));
+    TVC_TRY(tl.norm(l1, 1, kJ));
   } else {
-    const Acc* w1 = wv + Lt.woff[2];
-    if (d >= 4) {
-      Acc* w1b = c.at<Acc>(Lt.o_w1);
-      TVC_TRY(kron<Acc>(c, 2, d, w1b, nullptr, 1));
-      w1 = w1b;
-    }
-    Acc* w2 = c.at<Acc>(Lt.o_w2);
-    TVC_TRY(kron<Acc>(c, 0, 2, w2, f8 ? A->slab_scale : nullptr, n[1]));
-    Acc* Mm = c.at<Acc>(Lt.o_M);
-    Acc* Wa = c.at<Acc>(Lt.o_Wa);
-    const DualPlan p = plan_dual(A->dtype, Lt.n01, Lt.R1, a4);
-    TVC_TRY_HIP(run_dual(A->dtype, A->data, Lt.n01, Lt.R1, w1, w2, Mm, Wa,
-                         f8 ? A->slab_scale : nullptr, n[1], p, c.ws + Lt.o_dpart, c.s));
     TVC_TRY(run(c, Lt.acc_dt, Mm, n[0], n[1], 1, wv + Lt.woff[1], Y + Lt.woff[0], nullptr, 1));
     TVC_TRY(run(c, Lt.acc_dt, Mm, 1, n[0], n[1], wv + Lt.woff[0], Y + Lt.woff[1], nullptr, 1));
-    // y_m, m >= 2: W_2 contracted with every previous x_k, k >= 2, k != m,
-    // from the last mode down; the chain's last contraction writes y_m
-    for (int m = 2; m < d; ++m) {
-      const Acc* src = Wa;
-      Acc* bufs[2] = {c.at<Acc>(Lt.o_Ca), c.at<Acc>(Lt.o_Cb)};
-      int bi = 0;
-      const int last = m == 2 ? 3 : 2;   // mode of the chain's last contraction
-      i64 left = Lt.R1, right = 1;
-      for (int k = d - 1; k >= 2; --k) {
-        left /= n[k];
-        if (k == m) {
-          right = n[k];
-          continue;
-        }
-        Acc* dst = k == last ? Y + Lt.woff[m] : bufs[bi];
-        TVC_TRY(run(c, Lt.acc_dt, src, left, n[k], right, wv + Lt.woff[k], dst, nullptr, 1));
-        src = dst;
-        bi ^= 1;
-      }
-      ysrc[m] = src;   // W_2 itself when d = 3
-    }
+    TVC_TRY(tl.norm(TBuf::global(Y + Lt.woff[0], n[0]), 0, kJ));
+    TVC_TRY(tl.norm(TBuf::global(Y + Lt.woff[1], n[1]), 1, kJ));
   }
-  for (int j = 0; j < d; ++j) TVC_TRY(normalize<Acc>(c, ysrc[j], j, kAlignSign));
-  return TVC_OK;
+  // The leave-one-out vectors of a node of at most kTailIn values (modes
+  // [a, b)): for each kept mode j, contract the modes after j from the last
+  // one down, then the modes before j from the first one up.
+  Acc* Ca = c.at<Acc>(Lt.o_Ca);
+  Acc* Cb = c.at<Acc>(Lt.o_Cb);
+  auto leaf = [&](const TBuf& T, int a, int b) -> tvc_status {
+    for (int j = a; j < b; ++j) {
+      if (tl.room() < (b - a - 1) + 1 + 1) TVC_TRY(tl.flush());   // + 1: the mirror step
+      TBuf src = T;
+      i64 t = T.size;
+      auto next = [&](i64 out) {
+        if (out <= kTailElems) return TBuf::lds(tl_free_lds(src, src), out);
+        return TBuf::global(src.is_global() && src.ptr == Ca ? Cb : Ca, out);
+      };
+      for (int m = b - 1; m > j; --m) {
+        const i64 out = t / n[m];
+        const TBuf dst = next(out);
+        TVC_TRY(tl.last(src, out, n[m], m, dst));
+        src = dst;
+        t = out;
+      }
+      for (int m = a; m < j; ++m) {
+        const i64 out = t / n[m];
+        const TBuf dst = next(out);
+        TVC_TRY(tl.first(src, n[m], out, m, dst));
+        src = dst;
+        t = out;
+      }
+      TVC_TRY(tl.norm(src, j, kJ));
+    }
+    return TVC_OK;
+  };
+  // Nodes above kTailIn values: one pass over the node as a matrix (the
+  // halves' Kronecker weights from the previous vectors in x, which no
+  // launch so far has changed: the pending program runs after), then the
+  // two halves.  Same offsets as the workspace sizing.
+  Acc* J = c.at<Acc>(Lt.o_J);
+  Acc* uv = c.at<Acc>(Lt.o_w1);
+  i64 top = 0;
+  std::function<tvc_status(const TBuf&, int, int)> node = [&](const TBuf& T, int a, int b) -> tvc_status {
+    if (b - a <= 1 || T.size <= kTailIn) return leaf(T, a, b);
+    const int s2 = (b - a) / 2;
+    i64 P = 1;
+    for (int k = a; k < a + s2; ++k) P *= n[k];
+    const i64 Q = T.size / P;
+    Acc* mo = J + top;
+    Acc* zo = J + top + split_pad(P);
+    top += split_pad(P) + split_pad(Q);
+    TVC_TRY(kron<Acc>(c, a, a + s2, uv, nullptr, 1));
+    TVC_TRY(kron<Acc>(c, a + s2, b, uv + split_pad(P), nullptr, 1));
+    const DualPlan q = plan_dual(Lt.acc_dt, P, Q, true);
+    TVC_TRY_HIP(run_dual(Lt.acc_dt, T.ptr, P, Q, uv + split_pad(P), uv, mo, zo, nullptr, 1, q,
+                         c.ws + Lt.o_dpart, c.s));
+    TVC_TRY(node(TBuf::global(mo, P), a, a + s2));
+    return node(TBuf::global(zo, Q), a + s2, b);
+  };
+  TVC_TRY(node(TBuf::global(Wa, Lt.R1), 2, d));
+  TVC_TRY(tl.mirror());
+  return tl.flush();
 }
 
 template <typename Acc>

@@ -38,7 +38,10 @@ def check(traj, exact, x0, tol, form="chain"):
 
 
 SHAPES = [(40, 33), (300, 7), (9, 17, 5), (33, 40, 17), (6, 5, 7, 4), (4, 3, 5, 2, 6), (3, 4, 2, 3, 5, 2),
-          (3, 2, 5, 3, 2, 3, 7), (2, 3, 2, 2, 3, 2, 2, 5, 2, 3), (128, 1, 96), (2, 3, 1001), (5, 2, 4099)]
+          (3, 2, 5, 3, 2, 3, 7), (2, 3, 2, 2, 3, 2, 2, 5, 2, 3), (128, 1, 96), (2, 3, 1001), (5, 2, 4099),
+          # W = A x_0 x_0 x_1 x_1 above 8192 values: read once as a matrix of its
+          # halves (once; twice, the first half again; ragged odd halves)
+          (4, 3, 20, 21, 22), (2, 2, 5, 2000, 3, 2), (3, 2, 9, 11, 13, 7)]
 
 
 @pytest.mark.parametrize("fmt", ["f64", "f32"])
@@ -53,11 +56,26 @@ def test_jacobi_trajectory(dev, dims, fmt):
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "f16", "e4m3"])
-@pytest.mark.parametrize("dims", [(33, 40, 17), (12, 9, 10, 11), (64, 48), (2, 4, 1000)])
+@pytest.mark.parametrize("dims", [(33, 40, 17), (12, 9, 10, 11), (64, 48), (2, 4, 1000), (3, 2, 9, 11, 13, 7)])
 def test_jacobi_narrow_formats_on_stored_values(dev, fmt, dims):
     A, S, exact = stored_tensor(dims, fmt, 33, dev, kind="normal")
     x0 = synth.unit_vectors(dims, 34)
     check(run_jacobi(A, x0, 3, dev, scale=S), exact, x0, 2e-5)
+
+
+@pytest.mark.parametrize("dims", [(3, 2, 9, 11, 13, 7), (6, 5, 7, 4)], ids=lambda d: "x".join(map(str, d)))
+def test_jacobi_sweeps_in_one_call_equal_single_calls(dev, dims):
+    # each sweep reads the previous sweep's vectors from the mirror that the
+    # last step of the sweep before refreshed
+    A, _, _ = stored_tensor(dims, "f32", 35, dev, kind="normal")
+    x0 = synth.unit_vectors(dims, 36)
+    xa = tvc.pack_vectors(x0, dev)
+    ra = tvc.read_stats(tvc.hopm_jacobi_iterate(A, xa, 3))
+    xb = tvc.pack_vectors(x0, dev)
+    for _ in range(3):
+        rb = tvc.read_stats(tvc.hopm_jacobi_iterate(A, xb, 1))
+    assert torch.equal(xa, xb)
+    assert ra.lam == rb.lam and ra.delta == rb.delta and ra.sweeps == 3 and rb.sweeps == 1
 
 
 @pytest.mark.parametrize("dims", [(30, 20, 10), (8, 9, 7, 6), (50, 40)])
