@@ -26,7 +26,7 @@ namespace tvc {
 namespace {
 
 constexpr int kDualWaves = 4;            // waves per 256-thread workgroup
-constexpr i64 kDualTargetTasks = 4096;   // strips x chunks aimed at
+constexpr i64 kDualWavesPerCu = 16;      // resident waves per CU of a full grid
 constexpr i64 kDualMinRows = 16;         // rows per chunk, at least
 
 template <typename Acc>
@@ -349,7 +349,12 @@ DualPlan plan_dual(int dtype, i64 P, i64 R, bool a4, bool cols) {
   p.ucount = (R + eu - 1) / eu;
   p.nstrips = (p.ucount + (i64)kWave * cpt - 1) / ((i64)kWave * cpt);
   const i64 max_chunks = std::max<i64>(1, (P + kDualMinRows - 1) / kDualMinRows);
-  p.nchunks = std::max<i64>(1, std::min<i64>((kDualTargetTasks + p.nstrips - 1) / p.nstrips, max_chunks));
+  // Tasks are equal in size, so a round of them that the grid's waves do
+  // not fill is paid in full: at most one task per wave of a full grid
+  // where the strips allow it (measured: 63^5 pass 1, 245 strips, 4165 ->
+  // 3920 tasks).
+  const i64 waves = (i64)device_cus() * kDualWavesPerCu;
+  p.nchunks = std::max<i64>(1, std::min<i64>(waves / p.nstrips, max_chunks));
   p.rows_per_chunk = (P + p.nchunks - 1) / p.nchunks;
   p.nchunks = (P + p.rows_per_chunk - 1) / p.rows_per_chunk;
   const size_t ab = acc_bytes(dtype);
@@ -360,7 +365,7 @@ DualPlan plan_dual(int dtype, i64 P, i64 R, bool a4, bool cols) {
                                   cols ? align256((size_t)(fin_groups(p.nchunks) * R) * ab) : 0);
   p.part_bytes = p.m_part_bytes + p.z_part_bytes + t_bytes;
   const i64 tasks = p.nstrips * p.nchunks;
-  const i64 cap = (i64)device_cus() * 16 / kDualWaves;   // 16 waves per CU
+  const i64 cap = waves / kDualWaves;
   p.grid = (int)std::max<i64>(1, std::min<i64>((tasks + kDualWaves - 1) / kDualWaves, cap));
   return p;
 }
