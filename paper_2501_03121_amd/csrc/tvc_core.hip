@@ -55,7 +55,9 @@ constexpr int kCol1Unroll = TVC_COL1_UNROLL;    // column streaming with one wav
 template <int WV>
 struct ColwShape {
   static constexpr int kThreads = WV * kWave;
-  static constexpr int kUnroll = 32 / WV;
+  // 16 waves (E4M3 column strips with the window): 4 units in flight per
+  // lane, 64 KB per workgroup
+  static constexpr int kUnroll = WV >= 16 ? 4 : 32 / WV;
 };
 constexpr int kColwMaxM = 4096;  // weights staged in LDS by the column-strip kernel
 // Short rows with the window: a row-group reduction per row, so more waves
@@ -1637,10 +1639,12 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
       // beside it), a round of strips being at most half the window.
       if (p.nsplit == 1 && M <= kColwMaxM && !tuning().strips_off) {
         const bool win = win_ok(M, L * cdiv(nu, kWave));
-        // 8 waves of 4 loads for short strips (M < 32) and, with the window
-        // (one workgroup per CU), for E4M3, whose 16 conversions and FMAs per
-        // load need more waves to hide them (32^6 modes 1-3: 54-58 -> 61-66%)
-        const int wv = (M < 32 || (win && epv >= 16)) ? 8 : 4;
+        // 8 waves of 4 loads for short strips (M < 32); with the window (one
+        // workgroup per CU) E4M3, whose 16 conversions and FMAs per load need
+        // more waves and loads in flight to hide them, takes 16 waves of 4
+        // loads and one unit per lane (32^6 modes 1-3: 54-58% with 4 waves,
+        // 65-67% with 8, 70-74% with 16; 8^10 mode 5 41 -> 51%)
+        const int wv = (win && epv >= 16 && p.vec) ? 16 : (M < 32 || (win && epv >= 16)) ? 8 : 4;
         // with the window, several units per lane only where rows are a
         // multiple of 64 KB apart and less than 64 MB (measured on 32^6:
         // float32 mode 1, 4 MB rows, 75 -> 79%, bf16 mode 2, 64 KB rows,
@@ -1713,6 +1717,12 @@ void launch_colw_w(const TvcPlan& p, dim3 grd, hipStream_t st, const ColArgs<typ
 
 template <int DT, int ROLE>
 void launch_colw(const TvcPlan& p, dim3 grd, hipStream_t st, const ColArgs<typename St<DT>::Acc>& a) {
+  if constexpr (DT == TVC_F8E4M3) {
+    if (p.vec && p.wv == 16) {
+      launch_colw_c<DT, ROLE, true, 16, 1>(p, grd, st, a);
+      return;
+    }
+  }
   if (p.vec) {
     if (p.wv == 8) launch_colw_w<DT, ROLE, true, 8>(p, grd, st, a);
     else launch_colw_w<DT, ROLE, true, 4>(p, grd, st, a);
