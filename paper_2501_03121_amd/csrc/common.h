@@ -84,6 +84,9 @@ template <> __device__ __forceinline__ void unpack4<TVC_F8E4M3>(uint32_t w, floa
 // so rows whose length is not a whole number of 16-byte vectors (odd
 // extents in float32, say) still stream as dwordx4 loads and stores.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4), aligned(4)));
+// 16 bytes at any byte address: global loads on gfx950 need no alignment
+// (rows of 1- and 2-byte formats of odd length start on any byte)
+typedef unsigned int u32x4u __attribute__((ext_vector_type(4), aligned(1)));
 
 // Streaming loads of A use the nontemporal hint: every element is read once,
 // so it should not displace the vectors, weights and partial sums that are
@@ -94,9 +97,9 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4), aligned(4)));
 
 __device__ __forceinline__ uint4 stream_load16(const void* p) {
 #if TVC_NT_LOADS
-  const u32x4 v = __builtin_nontemporal_load((const u32x4*)p);
+  const u32x4u v = __builtin_nontemporal_load((const u32x4u*)p);
 #else
-  const u32x4 v = *(const u32x4*)p;
+  const u32x4u v = *(const u32x4u*)p;
 #endif
   uint4 r;
   __builtin_memcpy(&r, &v, 16);

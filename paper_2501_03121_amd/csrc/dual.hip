@@ -335,8 +335,9 @@ DualPlan plan_dual(int dtype, i64 P, i64 R, bool a4, bool cols) {
   p.cols = cols;
   const int epv = (int)(16 / elem_bytes(dtype));
   const size_t eb = elem_bytes(dtype);
-  // 16-byte units need dword-aligned rows at least one unit long
-  p.vec = a4 && R >= epv && ((size_t)R * eb) % 4 == 0;
+  // 16-byte units need rows at least one unit long, dword-aligned for 4-
+  // and 8-byte elements (1- and 2-byte formats load at any byte address)
+  p.vec = a4 && R >= epv && (((size_t)R * eb) % 4 == 0 || eb < 4);
   const int eu = p.vec ? epv : 1;
   int cpt;
   switch (dtype) {

@@ -1473,11 +1473,14 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
   const i64 epv = 16 / b;
   const size_t ab = acc_bytes(dtype);
   const int waves_per_block = kBlock / kWave;
-  // 16-byte units need every row of the contiguous extent to start on a
-  // dword boundary and to hold at least one unit; a ragged end (len mod EPV
-  // elements) is one more unit.
+  // 16-byte units need every row of the contiguous extent to hold at least
+  // one unit, and rows of 4- and 8-byte elements to start on a dword
+  // boundary; rows of 1- and 2-byte formats may start on any byte (odd
+  // lengths), since global loads need no alignment (bf16 30623^2, E4M3
+  // 13^8 and the like: one element per lane otherwise, 10-30% of peak).  A
+  // ragged end (len mod EPV elements) is one more unit.
   const i64 len = R == 1 ? M : R;
-  p.vec = a4 && (R != 1 || w4) && (len * b) % 4 == 0 && len >= epv;
+  p.vec = a4 && (R != 1 || w4) && ((len * b) % 4 == 0 || b < 4) && len >= epv;
   p.upr = p.vec ? len / epv : len;
   p.tail = p.vec ? (int)(len % epv) : 0;
   const i64 nu = p.upr + (p.tail > 0 ? 1 : 0);

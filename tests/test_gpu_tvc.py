@@ -160,6 +160,33 @@ def test_ragged_vector_rows(dev, fmt, no_stage):
             assert err <= TOL[fmt], (fmt, dims, k, alpha, beta, err)
 
 
+# Rows of 1- and 2-byte formats whose length is not a whole number of dwords
+# start on any byte; they still stream in 16-byte units (loaded at any byte
+# address), with a ragged end.
+UNALIGNED_LEN = {"f16": (1001, 13, 200001), "bf16": (1001, 13, 200001), "e4m3": (1001, 21, 200003)}
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16", "e4m3"])
+def test_unaligned_narrow_rows(dev, fmt, no_stage):
+    lg, sh, huge = UNALIGNED_LEN[fmt]
+    cases = [((37, lg), 1), ((37, lg), 0), ((3000, lg), 0), ((300, sh), 1), ((300, sh), 0),
+             ((50, 60, sh), 1), ((3, 5000, sh), 1), ((huge,), 0), ((2, 3, lg), 2), ((5, 7, lg), 1)]
+    for dims, k in cases:
+        A, S, exact = stored_tensor(dims, fmt, 15, dev)
+        p = tvc.contract_plan(A, k, scale=S)
+        contiguous = int(np.prod(dims[k + 1:])) if k + 1 < len(dims) else dims[k]
+        assert (contiguous * {"f16": 2, "bf16": 2, "e4m3": 1}[fmt]) % 4 != 0
+        assert p["vec"], (fmt, dims, k, p)
+        x, xh = vec(dims[k], 75 + k, fmt, dev)
+        for alpha, beta in ((1.0, 0.0), (0.5, -2.0)):
+            y0 = torch.from_numpy(synth.uniform(O.output_dims(dims, k), 85 + k))
+            out = y0.to(torch.float32).to(dev)
+            tvc.contract(A, x, k, alpha=alpha, beta=beta, out=out, scale=S)
+            ref = O.tvc(exact, xh, k, alpha=alpha, beta=beta, y=host(y0.to(torch.float32)))
+            err = O.rel_err(host(out), ref)
+            assert err <= TOL[fmt], (fmt, dims, k, alpha, beta, err)
+
+
 # Small slabs staged through LDS in blocks of whole slabs: rows of 33-64
 # 16-byte units, and slabs of at most 4 KB with a ragged, non-power-of-two or
 # very narrow right extent.  The cases cover a single partial block, a ragged
@@ -237,7 +264,10 @@ def test_weights_at_4_byte_offset(dev):
 # bit.
 def _window_cases(fmt):
     e = EPV[fmt]
-    return [((8, (3 << 22) + e // 2), 0), ((64, 12, 20001), 1), ((4096, 12, 40 * e + e // 2), 1)]
+    # rows of 20001 narrow elements load in 16-byte units like the others:
+    # more of them give enough strips for the window
+    lw = 64 if fmt in ("f32", "f64") else 256
+    return [((8, (3 << 22) + e // 2), 0), ((lw, 12, 20001), 1), ((4096, 12, 40 * e + e // 2), 1)]
 
 
 @pytest.mark.parametrize("fmt", FMTS)
