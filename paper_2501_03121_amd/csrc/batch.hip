@@ -254,6 +254,19 @@ __device__ bool wg_tile_done(uint32_t* counter, int ntiles, uint32_t* sh_flag) {
 
 // A pointer every lane holds the same value of (read from LDS), moved to
 // scalar registers.
+// Tile bytes in the global address space: the tensor pointers come from a
+// descriptor in memory, so without the address space the compiler issues
+// flat loads, which also count against the LDS counter (every LDS wait of
+// the window and the row-group combine then waits for them too).
+typedef const __attribute__((address_space(1))) char gchar;
+typedef const __attribute__((address_space(1))) u32x4u gu32x4;
+__device__ __forceinline__ uint4 tile_load16(gchar* p) {
+  const u32x4u v = __builtin_nontemporal_load((gu32x4*)p);
+  uint4 r;
+  __builtin_memcpy(&r, &v, 16);
+  return r;
+}
+
 __device__ __forceinline__ const char* uniform_ptr(const void* p) {
   const uint64_t v = (uint64_t)p;
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -307,7 +320,7 @@ __device__ void phase_p1(const BatchDesc& D, const InstLayout& L, float* s, int 
   const int sub = lane & (G - 1), rsub = lane >> g;
   const int wave = threadIdx.x / kWave;
   // the tile is far below 2^31 bytes: lanes address it with 32-bit offsets
-  const char* tbase = uniform_ptr(D.A + r0 * R);
+  gchar* tbase = (gchar*)uniform_ptr(D.A + r0 * R);
   for (int64_t c0 = r0; c0 < r1; c0 += kBWin) {
     const int64_t c1 = min(r1, c0 + kBWin);
     for (int64_t rb = c0 + (int64_t)wave * P * RU; rb < c1; rb += (int64_t)NW * P * RU) {
@@ -323,8 +336,11 @@ __device__ void phase_p1(const BatchDesc& D, const InstLayout& L, float* s, int 
         uint4 raw[RU];
 #pragma unroll
         for (int j = 0; j < RU; ++j) {
-          const int64_t row = rb + (int64_t)j * P + rsub;
-          raw[j] = row < c1 ? stream_load16(tbase + (uint32_t)(((row - r0) * R + e) * 4)) : uint4{0u, 0u, 0u, 0u};
+          // rows past the window's end re-read its last row (never stored):
+          // no branch per load
+          int64_t row = rb + (int64_t)j * P + rsub;
+          row = row < c1 ? row : c1 - 1;
+          raw[j] = tile_load16(tbase + (uint32_t)(((row - r0) * R + e) * 4));
         }
 #pragma unroll
         for (int j = 0; j < RU; ++j) {
@@ -373,7 +389,7 @@ __device__ void phase_p2(const BatchDesc& D, const InstLayout& L, float* s, int 
   while (((int64_t)1 << g) < nu && g < 8) ++g;
   const int TC = 1 << g, RG = kBThreads >> g;
   const int tc = threadIdx.x & (TC - 1), rg = threadIdx.x >> g;
-  const char* tbase = uniform_ptr(D.A + r0 * R);   // 32-bit lane offsets below
+  gchar* tbase = (gchar*)uniform_ptr(D.A + r0 * R);   // 32-bit lane offsets below
   int64_t wc0 = 0;  // first column held by the window
   for (int64_t cb = 0; cb < nu; cb += TC) {
     if ((cb + TC) * 4 - wc0 > kBWin) {  // this block's columns would not fit
@@ -383,7 +399,8 @@ __device__ void phase_p2(const BatchDesc& D, const InstLayout& L, float* s, int 
     const int64_t u = cb + tc;
     const bool on = u < nu;
     const bool tl = T != 0 && u == U;
-    const int64_t e = tl ? R - 4 : u * 4;
+    // lanes past the row's units load its last unit (never stored)
+    const int64_t e = tl || !on ? R - 4 : u * 4;
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
     for (int64_t row = r0 + rg; row < r1; row += (int64_t)RG * UN) {
       uint4 raw[UN];
@@ -392,8 +409,11 @@ __device__ void phase_p2(const BatchDesc& D, const InstLayout& L, float* s, int 
       for (int k = 0; k < UN; ++k) {
         const int64_t rk = row + (int64_t)k * RG;
         const bool ok = rk < r1;
-        raw[k] = (on && ok) ? stream_load16(tbase + (uint32_t)(((rk - r0) * R + e) * 4)) : uint4{0u, 0u, 0u, 0u};
-        wr[k] = ok ? w2[rk] : 0.f;
+        // rows past the tile re-read its last row with weight 0 (A is finite)
+        const int64_t rc = ok ? rk : r1 - 1;
+        raw[k] = tile_load16(tbase + (uint32_t)(((rc - r0) * R + e) * 4));
+        const float wk = w2[rc];
+        wr[k] = ok ? wk : 0.f;
       }
 #pragma unroll
       for (int k = 0; k < UN; ++k) {
