@@ -27,6 +27,7 @@ namespace {
 
 constexpr int kDualWaves = 4;            // waves per 256-thread workgroup
 constexpr i64 kDualWavesPerCu = 16;      // resident waves per CU of a full grid
+constexpr i64 kDualTaskBytes = 32768;    // a task's fixed cost, in bytes of its strip's rows
 constexpr i64 kDualMinRows = 16;         // rows per chunk, at least
 
 template <typename Acc>
@@ -351,11 +352,34 @@ DualPlan plan_dual(int dtype, i64 P, i64 R, bool a4, bool cols) {
   p.nstrips = (p.ucount + (i64)kWave * cpt - 1) / ((i64)kWave * cpt);
   const i64 max_chunks = std::max<i64>(1, (P + kDualMinRows - 1) / kDualMinRows);
   // Tasks are equal in size, so a round of them that the grid's waves do
-  // not fill is paid in full: at most one task per wave of a full grid
-  // where the strips allow it (measured: 63^5 pass 1, 245 strips, 4165 ->
-  // 3920 tasks).
+  // not fill is paid in full: the row chunks minimise rounds x (rows per
+  // task + h), h the rows of a strip that stand for a task's fixed cost
+  // (its strip's weights, its row partials: kDualTaskBytes).  Measured: 63^5 pass 1, 245
+  // strips, 4165 -> 3920 tasks, sweep 66 -> 73%; 13^8, 4714 strips of 169
+  // rows, 1 -> 5 chunks, 68 -> 72%; Jacobi 19^7, 2419 strips, 1 -> 5
+  // chunks, 50 -> 60%).  With the column sums every chunk adds R partials
+  // (at most 1/32 of A's bytes, or 16 MB), and with more strips than waves they cost
+  // more than the partly filled last round (Jacobi 13^8 and 10^9: 58 and
+  // 63% with one chunk, 53 and 56% with 5 and 2): one chunk there.
   const i64 waves = (i64)device_cus() * kDualWavesPerCu;
-  p.nchunks = std::max<i64>(1, std::min<i64>(waves / p.nstrips, max_chunks));
+  const size_t ab0 = acc_bytes(dtype);
+  i64 cmax = std::min<i64>(max_chunks, 4 * ((waves + p.nstrips - 1) / p.nstrips) + 64);
+  if (cols)
+    cmax = std::min<i64>(cmax, std::max<i64>({(i64)1, P * (i64)eb / (32 * (i64)ab0),
+                                              ((i64)16 << 20) / (R * (i64)ab0)}));
+  const i64 h = std::max<i64>(1, kDualTaskBytes / ((i64)kWave * cpt * eu * (i64)eb));
+  if (cols && p.nstrips > waves) cmax = 1;
+  i64 best = -1;
+  p.nchunks = 1;
+  for (i64 c = 1; c <= cmax; ++c) {
+    const i64 rpc = (P + c - 1) / c;
+    const i64 tasks = p.nstrips * ((P + rpc - 1) / rpc);
+    const i64 t = (tasks + waves - 1) / waves * (rpc + h);
+    if (best < 0 || t < best) {
+      best = t;
+      p.nchunks = c;
+    }
+  }
   p.rows_per_chunk = (P + p.nchunks - 1) / p.nchunks;
   p.nchunks = (P + p.rows_per_chunk - 1) / p.rows_per_chunk;
   const size_t ab = acc_bytes(dtype);
