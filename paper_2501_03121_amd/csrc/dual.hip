@@ -369,17 +369,22 @@ DualPlan plan_dual(int dtype, i64 P, i64 R, bool a4, bool cols) {
                                               ((i64)16 << 20) / (R * (i64)ab0)}));
   const i64 h = std::max<i64>(1, kDualTaskBytes / ((i64)kWave * cpt * eu * (i64)eb));
   if (cols && p.nstrips > waves) cmax = 1;
+  // Candidates (the planner runs on every sweep, so no long search): up to
+  // 64 chunks, and the chunk counts that fill 1..16 whole rounds.
   i64 best = -1;
   p.nchunks = 1;
-  for (i64 c = 1; c <= cmax; ++c) {
+  auto consider = [&](i64 c) {
+    if (c < 1 || c > cmax) return;
     const i64 rpc = (P + c - 1) / c;
     const i64 tasks = p.nstrips * ((P + rpc - 1) / rpc);
     const i64 t = (tasks + waves - 1) / waves * (rpc + h);
-    if (best < 0 || t < best) {
+    if (best < 0 || t < best || (t == best && c < p.nchunks)) {
       best = t;
       p.nchunks = c;
     }
-  }
+  };
+  for (i64 c = 1; c <= 64; ++c) consider(c);
+  for (i64 k = 1; k <= 16; ++k) consider(k * waves / p.nstrips);
   p.rows_per_chunk = (P + p.nchunks - 1) / p.nchunks;
   p.nchunks = (P + p.rows_per_chunk - 1) / p.rows_per_chunk;
   const size_t ab = acc_bytes(dtype);
