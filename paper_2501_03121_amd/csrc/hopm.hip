@@ -375,7 +375,7 @@ struct Layout {
   i64 nsum = 0, nmax = 0, N = 0, R1 = 1, n01 = 1;
   // byte offsets into ws
   size_t o_wv = 0, o_y = 0, o_M = 0, o_w1 = 0, o_w2 = 0, o_Wa = 0, o_Wb = 0, o_Ca = 0, o_Cb = 0,
-         o_stats = 0, o_part = 0, o_Y = 0, o_J = 0, o_dpart = 0;
+         o_stats = 0, o_part = 0, o_Y = 0, o_J = 0, o_uv = 0, o_dpart = 0;
   size_t part_bytes = 0, dpart_bytes = 0;
   size_t total = 0;
 };
@@ -496,13 +496,15 @@ Layout make_layout(const tvc_tensor* A) {
   // Jacobi sweeps: the d contraction results, the outputs of the halving
   // of W, and the one-pass scratch
   Lt.o_Y = take((size_t)Lt.wsum * ab);
-  i64 jtop = 0;
+  i64 jtop = 0, uvmax = 0;
   size_t jpart = 0;
   if (Lt.d >= 4)
     jacobi_splits(Lt.n, 2, Lt.d, Lt.R1, jtop, [&](int, int, int, i64 P, i64 Q, i64, i64) {
       for (int a4 = 0; a4 < 2; ++a4) jpart = std::max(jpart, plan_dual(Lt.acc_dt, P, Q, a4).part_bytes);
+      uvmax = std::max(uvmax, split_pad(P) + Q);   // the two halves' Kronecker weights
     });
   Lt.o_J = take((size_t)jtop * ab);
+  Lt.o_uv = take((size_t)uvmax * ab);
   const i64 P = Lt.d >= 3 ? Lt.n01 : Lt.n[0];
   const i64 R = Lt.d >= 3 ? Lt.R1 : (Lt.d == 2 ? Lt.n[1] : 1);
   // the one-pass scratch also serves pass 1 as strips (rows only)
@@ -940,7 +942,7 @@ tvc_status jacobi_sweep(const Ctx& c) {
   // launch so far has changed: the pending program runs after), then the
   // two halves.  Same offsets as the workspace sizing.
   Acc* J = c.at<Acc>(Lt.o_J);
-  Acc* uv = c.at<Acc>(Lt.o_w1);
+  Acc* uv = c.at<Acc>(Lt.o_uv);
   i64 top = 0;
   std::function<tvc_status(const TBuf&, int, int)> node = [&](const TBuf& T, int a, int b) -> tvc_status {
     if (b - a <= 1 || T.size <= kTailIn) return leaf(T, a, b);

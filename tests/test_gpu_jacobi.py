@@ -41,7 +41,9 @@ SHAPES = [(40, 33), (300, 7), (9, 17, 5), (33, 40, 17), (6, 5, 7, 4), (4, 3, 5, 
           (3, 2, 5, 3, 2, 3, 7), (2, 3, 2, 2, 3, 2, 2, 5, 2, 3), (128, 1, 96), (2, 3, 1001), (5, 2, 4099),
           # W = A x_0 x_0 x_1 x_1 above 8192 values: read once as a matrix of its
           # halves (once; twice, the first half again; ragged odd halves)
-          (4, 3, 20, 21, 22), (2, 2, 5, 2000, 3, 2), (3, 2, 9, 11, 13, 7)]
+          (4, 3, 20, 21, 22), (2, 2, 5, 2000, 3, 2), (3, 2, 9, 11, 13, 7),
+          # size-1 modes in W: one-row matrices and one-value halves
+          (4, 4, 1, 1, 9000), (2, 3, 1, 5000, 1, 3)]
 
 
 @pytest.mark.parametrize("fmt", ["f64", "f32"])
