@@ -175,7 +175,8 @@ def hopm_iterate(A: torch.Tensor, x: torch.Tensor, sweeps: int = 1, scale: torch
     if ws is None:
         ws = _WS.get(need, A.device)
     if stats is None:
-        stats = torch.zeros(32, dtype=torch.uint8, device=A.device)
+        # the library's first step writes every field of the record
+        stats = torch.empty(32, dtype=torch.uint8, device=A.device)
     L.check(lib.hopm_iterate(desc, x.data_ptr(), int(sweeps), _WS.ptr(ws), int(need),
                              stats.data_ptr(), _stream()))
     return stats
@@ -195,7 +196,8 @@ def hopm_jacobi_iterate(A: torch.Tensor, x: torch.Tensor, sweeps: int = 1,
     if ws is None:
         ws = _WS.get(need, A.device)
     if stats is None:
-        stats = torch.zeros(32, dtype=torch.uint8, device=A.device)
+        # the library's first step writes every field of the record
+        stats = torch.empty(32, dtype=torch.uint8, device=A.device)
     L.check(lib.hopm_jacobi_iterate(desc, x.data_ptr(), int(sweeps), _WS.ptr(ws), int(need),
                                     stats.data_ptr(), _stream()))
     return stats
