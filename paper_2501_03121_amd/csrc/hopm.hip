@@ -374,51 +374,25 @@ struct Layout {
   i64 wsum = 0;
   i64 nsum = 0, nmax = 0, N = 0, R1 = 1, n01 = 1;
   // byte offsets into ws
-  size_t o_wv = 0, o_y = 0, o_M = 0, o_w1 = 0, o_w2 = 0, o_Wa = 0, o_Wb = 0, o_Ca = 0, o_Cb = 0,
-         o_stats = 0, o_part = 0, o_Y = 0, o_J = 0, o_uv = 0, o_dpart = 0;
+  size_t o_wv = 0, o_y = 0, o_M = 0, o_w1 = 0, o_w2 = 0, o_Wa = 0, o_Ca = 0, o_Cb = 0,
+         o_stats = 0, o_part = 0, o_Y = 0, o_J = 0, o_uv = 0, o_L = 0, o_dpart = 0;
   size_t part_bytes = 0, dpart_bytes = 0;
   size_t total = 0;
 };
-
-// Every contraction a sweep performs, as (dtype, L, M, R); the workspace
-// must hold the largest partial-sum scratch among them.
-void sweep_tvcs(const Layout& Lt, std::vector<std::array<i64, 4>>& out) {
-  const int d = Lt.d;
-  const i64* n = Lt.n;
-  if (d == 2) {
-    out.push_back({Lt.dt, n[0], n[1], 1});
-    out.push_back({Lt.dt, 1, n[0], n[1]});
-    return;
-  }
-  out.push_back({Lt.dt, Lt.n01, Lt.R1, 1});            // pass 1
-  out.push_back({Lt.acc_dt, n[0], n[1], 1});           // M x_1
-  out.push_back({Lt.acc_dt, 1, n[0], n[1]});           // M^T x_0
-  out.push_back({Lt.dt, 1, Lt.n01, Lt.R1});            // pass 2
-  i64 wsize = Lt.R1;
-  for (int j = 2; j < d; ++j) {
-    if (j > 2) {
-      out.push_back({Lt.acc_dt, 1, n[j - 1], wsize / n[j - 1]});
-      wsize /= n[j - 1];
-    }
-    i64 t = wsize;
-    for (int m = d - 1; m > j; --m) {
-      out.push_back({Lt.acc_dt, t / n[m], n[m], 1});
-      t /= n[m];
-    }
-  }
-}
 
 // Inputs in global memory up to this many values are read by the single
 // workgroup of a small-step program (about 32 KB in float32: a few
 // microseconds); larger ones get a full launch.
 constexpr i64 kTailIn = 8192;
 
-// Jacobi sweeps take the leave-one-out vectors of W = A x_0 x_0 x_1 x_1
+// Both sweeps take the vectors of the modes of W = A x_0 x_0 x_1 x_1
 // (modes 2..d-1 kept) by halving: a node holding modes [a, b) of more than
-// kTailIn values is read once as the matrix [modes a..a+s)][modes a+s..b),
+// kTailIn values is read as the matrix [modes a..a+s)][modes a+s..b),
 // s = (b - a) / 2, giving its contractions over the second half (the
-// first-half node) and over the first half (the second-half node); nodes
-// of at most kTailIn values go to the small-step program.  Every node's
+// first-half node) and over the first half (the second-half node): in one
+// pass for a Jacobi sweep, in two for a Gauss-Seidel sweep, whose second
+// contraction takes the first half's new vectors; nodes of at most kTailIn
+// values go to the small-step program.  Every node's
 // two outputs get their own stretch of the split buffer (a pending
 // small-step program may still read an earlier one), taken in the order the
 // sweep visits the nodes.  f(a, s, b, P, Q, mo, zo) per split: P x Q the
@@ -437,6 +411,43 @@ void jacobi_splits(const i64* n, int a, int b, i64 size, i64& top, F&& f) {
   f(a, s, b, P, Q, mo, zo);
   jacobi_splits(n, a, a + s, P, top, f);
   jacobi_splits(n, a + s, b, Q, top, f);
+}
+
+// Every contraction a sweep performs, as (dtype, L, M, R); the workspace
+// must hold the largest partial-sum scratch among them.
+void sweep_tvcs(const Layout& Lt, std::vector<std::array<i64, 4>>& out) {
+  const int d = Lt.d;
+  const i64* n = Lt.n;
+  if (d == 2) {
+    out.push_back({Lt.dt, n[0], n[1], 1});
+    out.push_back({Lt.dt, 1, n[0], n[1]});
+    return;
+  }
+  out.push_back({Lt.dt, Lt.n01, Lt.R1, 1});            // pass 1
+  out.push_back({Lt.acc_dt, n[0], n[1], 1});           // M x_1
+  out.push_back({Lt.acc_dt, 1, n[0], n[1]});           // M^T x_0
+  out.push_back({Lt.dt, 1, Lt.n01, Lt.R1});            // pass 2
+  // the halving of W_2 (rows, then columns, of each node above kTailIn
+  // values); the one-pass kernel of Jacobi sweeps sizes its own scratch
+  i64 top = 0;
+  if (d >= 4)
+    jacobi_splits(n, 2, d, Lt.R1, top, [&](int, int, int, i64 P, i64 Q, i64, i64) {
+      out.push_back({Lt.acc_dt, P, Q, 1});
+      out.push_back({Lt.acc_dt, 1, P, Q});
+    });
+  // the leave-one-out chains on W_2 of hopm_leave_one_out: each contracts
+  // modes k = d-1 .. 2 except the kept mode m
+  for (int m = 2; m < d; ++m) {
+    i64 left = Lt.R1, right = 1;   // left: modes before k still present
+    for (int k = d - 1; k >= 2; --k) {
+      left /= n[k];
+      if (k == m) {
+        right = n[k];
+        continue;
+      }
+      out.push_back({Lt.acc_dt, left, n[k], right});
+    }
+  }
 }
 
 Layout make_layout(const tvc_tensor* A) {
@@ -475,7 +486,6 @@ Layout make_layout(const tvc_tensor* A) {
     Lt.o_w2 = take((size_t)Lt.n01 * ab);
     Lt.o_w1 = take(Lt.d >= 4 ? (size_t)Lt.R1 * ab : 0);
     Lt.o_Wa = take((size_t)Lt.R1 * ab);
-    Lt.o_Wb = take(Lt.d >= 4 ? (size_t)(Lt.R1 / Lt.n[2]) * ab : 0);
     i64 nmin = Lt.R1;
     for (int k = 2; k < Lt.d; ++k) nmin = std::min(nmin, Lt.n[k]);
     const size_t c = Lt.d >= 4 ? (size_t)(Lt.R1 / nmin) * ab : 0;
@@ -493,8 +503,8 @@ Layout make_layout(const tvc_tensor* A) {
         pb = std::max(pb, plan_tvc((int)t[0], t[1], t[2], t[3], a16, w16).part_bytes);
   Lt.part_bytes = pb;
   Lt.o_part = take(pb);
-  // Jacobi sweeps: the d contraction results, the outputs of the halving
-  // of W, and the one-pass scratch
+  // Jacobi sweeps: the d contraction results; both sweeps: the outputs and
+  // the Kronecker weights of the halving of W; the one-pass scratch
   Lt.o_Y = take((size_t)Lt.wsum * ab);
   i64 jtop = 0, uvmax = 0;
   size_t jpart = 0;
@@ -505,6 +515,8 @@ Layout make_layout(const tvc_tensor* A) {
     });
   Lt.o_J = take((size_t)jtop * ab);
   Lt.o_uv = take((size_t)uvmax * ab);
+  // the leaves' global buffers of a Gauss-Seidel sweep
+  Lt.o_L = take(Lt.d >= 3 ? (size_t)(3 * kTailIn) * ab : 0);
   const i64 P = Lt.d >= 3 ? Lt.n01 : Lt.n[0];
   const i64 R = Lt.d >= 3 ? Lt.R1 : (Lt.d == 2 ? Lt.n[1] : 1);
   // the one-pass scratch also serves pass 1 as strips (rows only)
@@ -738,9 +750,6 @@ tvc_status sweep(const Ctx& c) {
   Acc* Mm = c.at<Acc>(Lt.o_M);
   Acc* w2 = c.at<Acc>(Lt.o_w2);
   Acc* Wa = c.at<Acc>(Lt.o_Wa);
-  Acc* Wb = c.at<Acc>(Lt.o_Wb);
-  Acc* Ca = c.at<Acc>(Lt.o_Ca);
-  Acc* Cb = c.at<Acc>(Lt.o_Cb);
   typedef TBufT<Acc> TBuf;
   Tail<Acc> tl(c);
   // pass 1: M = A contracted over modes 2..d-1
@@ -775,63 +784,83 @@ tvc_status sweep(const Ctx& c) {
   }
   // pass 2: W_2 = A contracted with x_0 (x) x_1 (slab scale folded into the weights)
   TVC_TRY(run(c, A->dtype, A->data, 1, Lt.n01, Lt.R1, w2, Wa, nullptr, 1));
-  // j >= 2.  A step whose input is in global memory and larger than kTailIn
-  // values is a full launch (after the pending program, whose vectors it
-  // may need); smaller steps join the program, with outputs in LDS when
-  // they fit.
-  TBuf W = TBuf::global(Wa, Lt.R1);
-  Acc* wfree = Wb;   // the global W buffer not holding W
-  for (int j = 2; j < d; ++j) {
-    // j's steps (at most one contraction of W, d - 1 - j of the chain and the
-    // normalisation) stay in one program, since they pass values through LDS.
-    // If they do not fit the pending program, it is run first; W moves to a
-    // global buffer beforehand when it lives in LDS (high orders, small dims).
-    if (tl.room() < (j > 2 ? 1 : 0) + (d - 1 - j) + 1 + 1) {   // + 1: the copy of W
-      if (!W.is_global()) {
-        const TBuf dst = TBuf::global(Wa, W.size);
-        TVC_TRY(tl.copy(W, dst));
-        W = dst;
-        wfree = Wb;
-      }
-      TVC_TRY(tl.flush());
-    }
-    if (j > 2) {   // W_j = W_{j-1} contracted over its first mode (j - 1)
-      const i64 out = W.size / n[j - 1];
-      if (W.is_global() && W.size > kTailIn) {
+  // j >= 2: the modes of W_2 in Gauss-Seidel order, by halving (see
+  // jacobi_splits for the node layout).  A node T holding modes [a, b) and
+  // more than kTailIn values is read as the matrix [modes a..h)[modes h..b):
+  // its rows against the previous x_h..x_{b-1} give the node of the first
+  // half, whose vectors are then updated in order; its columns against those
+  // new x_a..x_{h-1} give the node of the second half.  Each x_j thus sees
+  // the new vectors of the modes before it and the previous ones of the
+  // modes after it, as in the chain of Algorithm 1, and W_2 is read twice per
+  // level instead of once per kept mode.  Nodes of at most kTailIn values
+  // run the chain in the small-step program.
+  Acc* J = c.at<Acc>(Lt.o_J);
+  Acc* uv = c.at<Acc>(Lt.o_uv);
+  Acc* const Lb[3] = {c.at<Acc>(Lt.o_L), c.at<Acc>(Lt.o_L) + kTailIn, c.at<Acc>(Lt.o_L) + 2 * kTailIn};
+  // a leaf buffer holding neither x1 nor x2
+  auto lfree = [&](const TBuf& x1, const TBuf& x2) -> Acc* {
+    for (Acc* q : Lb)
+      if (!(x1.is_global() && x1.ptr == q) && !(x2.is_global() && x2.ptr == q)) return q;
+    return Lb[0];
+  };
+  auto leaf = [&](const TBuf& T, int a, int b) -> tvc_status {
+    TBuf W = T;
+    for (int j = a; j < b; ++j) {
+      // j's steps (at most one contraction of W, b - 1 - j of the chain and
+      // the normalisation) pass values through LDS, so they share a program;
+      // W moves to a global buffer first when the pending one must be run.
+      if (tl.room() < (j > a ? 1 : 0) + (b - 1 - j) + 1 + 1) {   // + 1: the copy of W
+        if (!W.is_global()) {
+          const TBuf dst = TBuf::global(lfree(W, W), W.size);
+          TVC_TRY(tl.copy(W, dst));
+          W = dst;
+        }
         TVC_TRY(tl.flush());
-        TVC_TRY(run(c, Lt.acc_dt, W.ptr, 1, n[j - 1], out, wv + Lt.woff[j - 1], wfree, nullptr, 1));
-        Acc* old = W.ptr;
-        W = TBuf::global(wfree, out);
-        wfree = old;
-      } else {
-        TBuf dst = out <= kTailElems ? TBuf::lds(tl_free_lds(W, W), out)
-                                     : TBuf::global(W.is_global() && W.ptr == Wa ? Wb : Wa, out);
+      }
+      if (j > a) {   // W_j = W_{j-1} contracted over its first mode (j - 1), new x_{j-1}
+        const i64 out = W.size / n[j - 1];
+        const TBuf dst = out <= kTailElems ? TBuf::lds(tl_free_lds(W, W), out)
+                                           : TBuf::global(lfree(W, W), out);
         TVC_TRY(tl.first(W, n[j - 1], out, j - 1, dst));
-        if (dst.is_global()) wfree = (dst.ptr == Wa) ? Wb : Wa;
         W = dst;
       }
-    }
-    // y_j = W_j contracted over modes d-1 .. j+1
-    TBuf src = W;
-    i64 t = W.size;
-    for (int m = d - 1; m > j; --m) {
-      const i64 out = t / n[m];
-      TBuf dst;
-      if (src.is_global() && t > kTailIn) {
-        TVC_TRY(tl.flush());
-        Acc* o = (m == j + 1) ? y : ((src.ptr == Ca) ? Cb : Ca);
-        TVC_TRY(run(c, Lt.acc_dt, src.ptr, out, n[m], 1, wv + Lt.woff[m], o, nullptr, 1));
-        dst = TBuf::global(o, out);
-      } else {
-        dst = out <= kTailElems ? TBuf::lds(tl_free_lds(W, src), out)
-                                : TBuf::global((src.is_global() && src.ptr == Ca) ? Cb : Ca, out);
+      // y_j = W_j contracted over modes b-1 .. j+1 (previous vectors)
+      TBuf src = W;
+      i64 t = W.size;
+      for (int m = b - 1; m > j; --m) {
+        const i64 out = t / n[m];
+        const TBuf dst = out <= kTailElems ? TBuf::lds(tl_free_lds(W, src), out)
+                                           : TBuf::global(lfree(W, src), out);
         TVC_TRY(tl.last(src, out, n[m], m, dst));
+        src = dst;
+        t = out;
       }
-      src = dst;
-      t = out;
+      TVC_TRY(tl.norm(src, j));
     }
-    TVC_TRY(tl.norm(src, j));
-  }
+    return TVC_OK;
+  };
+  i64 top = 0;
+  std::function<tvc_status(const TBuf&, int, int)> node = [&](const TBuf& T, int a, int b) -> tvc_status {
+    if (b - a <= 1 || T.size <= kTailIn) return leaf(T, a, b);
+    const int h = a + (b - a) / 2;
+    i64 P = 1;
+    for (int k = a; k < h; ++k) P *= n[k];
+    const i64 Q = T.size / P;
+    Acc* vo = J + top;
+    Acc* uo = J + top + split_pad(P);
+    top += split_pad(P) + split_pad(Q);
+    // first half: rows against the previous x_h..x_{b-1} (no pending step
+    // has changed them)
+    TVC_TRY(kron<Acc>(c, h, b, uv + split_pad(P), nullptr, 1));
+    TVC_TRY(run(c, Lt.acc_dt, T.ptr, P, Q, 1, uv + split_pad(P), vo, nullptr, 1));
+    TVC_TRY(node(TBuf::global(vo, P), a, h));
+    // second half: columns against the new x_a..x_{h-1} (their program first)
+    TVC_TRY(tl.flush());
+    TVC_TRY(kron<Acc>(c, a, h, uv, nullptr, 1));
+    TVC_TRY(run(c, Lt.acc_dt, T.ptr, 1, P, Q, uv, uo, nullptr, 1));
+    return node(TBuf::global(uo, Q), h, b);
+  };
+  TVC_TRY(node(TBuf::global(Wa, Lt.R1), 2, d));
   return tl.flush();
 }
 
