@@ -1,5 +1,5 @@
 """Parity at the benchmark's full sizes and launch configuration: 1024^3 and
-32^6 float32 tensors (4.3 GB each).  Contractions are checked on sampled
+32^6 float32 tensors (4.3 GB each) and their bf16, fp16 and E4M3 stored copies.  Contractions are checked on sampled
 outputs that the oracle computes one by one from the exact host copy of the
 device bytes; HOPM sweeps against the float64 canonical oracle from the same
 start vectors."""
@@ -43,6 +43,60 @@ def test_full_size_tvc_sampled(dev, dims):
         yb = host(tvc.contract(Ab, x, k)).reshape(u, v)[lr[:, 0], lr[:, 1]]
         refb = O.tvc_sample(Abh, xh, k, lr)
         assert O.rel_err(yb, refb) < 1e-5, ("bf16", dims, k)
+
+
+class _Stored:
+    """A stored tensor's codes; indexing a fiber [l, :, r] of its (u, n, v)
+    view decodes that fiber alone to the exact values the codes stand for
+    (the oracle's decoders; E4M3 codes times their mode-0 slab scale), so
+    that the oracle can sample a full-size tensor without decoding it all."""
+
+    def __init__(self, codes, decode, scale=None, view=None):
+        self.codes, self.decode, self.scale = codes, decode, scale
+        self.shape = codes.shape if view is None else view
+
+    def reshape(self, u, n, v):
+        return _Stored(self.codes, self.decode, self.scale, (u, n, v))
+
+    def __getitem__(self, idx):
+        l, _, r = idx
+        _, n, v = self.shape
+        flat = (l * n + np.arange(n, dtype=np.int64)) * v + r
+        vals = self.decode(self.codes.reshape(-1)[flat])
+        if self.scale is not None:
+            slab = self.codes.size // self.codes.shape[0]
+            vals = vals * self.scale.astype(np.float64)[flat // slab]
+        return vals
+
+
+@pytest.mark.parametrize("fmt", ["f16", "e4m3"])
+@pytest.mark.parametrize("dims", SHAPES, ids=["1024^3", "32^6"])
+def test_full_size_narrow_stored_values(dev, dims, fmt):
+    # stored-value parity of fp16 and E4M3 (slab scales included) at full
+    # size, every mode, on sampled outputs, each within 1e-5 of the
+    # magnitude sum of its own terms
+    A = synth.device_normal(dims, 100, dev)
+    Aq, S = tvc.quantize(A, fmt)
+    del A
+    torch.cuda.empty_cache()
+    if fmt == "f16":
+        codes, dec = Aq.cpu().view(torch.int16).numpy().view(np.uint16), Q.f16_to_f64
+    else:
+        codes, dec = Aq.cpu().view(torch.uint8).numpy(), Q.e4m3_to_f64
+    scale = None if S is None else S.cpu().numpy()
+    exact = _Stored(codes, dec, scale)
+    mag = _Stored(codes, lambda c: np.abs(dec(c)), scale)
+    for k in range(len(dims)):
+        xh = synth.unit_vectors([dims[k]], 300 + k)[0].astype(np.float32)
+        x = torch.from_numpy(xh).to(dev)
+        lr = sample_lr(dims, k, 7 + k)
+        u, _, v = O.matricized_dims(dims, k)
+        y = host(tvc.contract(Aq, x, k, scale=S)).reshape(u, v)[lr[:, 0], lr[:, 1]]
+        ref = O.tvc_sample(exact, xh, k, lr)
+        bound = O.tvc_sample(mag, np.abs(xh), k, lr)
+        assert O.rel_err(y, ref) < 1e-5, (fmt, dims, k, O.rel_err(y, ref))
+        worst = np.max(np.abs(y - ref) / bound)
+        assert worst <= 1e-5, (fmt, dims, k, worst)
 
 
 @pytest.mark.parametrize("dims", SHAPES, ids=["1024^3", "32^6"])
