@@ -9,7 +9,7 @@ import paper_2501_03121_amd as tvc
 from oracle import quant as Q
 from oracle import tvc as O
 from paper_2501_03121_amd import synth
-from _util import TOL, host, stored_tensor, vec
+from _util import TOL, assert_elementwise, host, stored_tensor, vec
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +43,9 @@ def test_parity_all_modes(dev, fmt, dims):
         err = O.rel_err(host(y), ref)
         assert y.shape == ref.shape
         assert err <= TOL[fmt], (fmt, dims, k, err)
+        # and every output on its own
+        assert_elementwise(host(y), ref, O.tvc(np.abs(exact), np.abs(xh), k), dims[k], fmt,
+                           (dims, k))
 
 
 @pytest.mark.parametrize("fmt", ["f64", "f32", "f16", "bf16"])
@@ -158,6 +161,8 @@ def test_ragged_vector_rows(dev, fmt, no_stage):
             ref = O.tvc(exact, xh, k, alpha=alpha, beta=beta, y=host(y0))
             err = O.rel_err(host(out), ref)
             assert err <= TOL[fmt], (fmt, dims, k, alpha, beta, err)
+            mag = abs(alpha) * O.tvc(np.abs(exact), np.abs(xh), k) + abs(beta) * np.abs(host(y0))
+            assert_elementwise(host(out), ref, mag, dims[k], fmt, (dims, k, alpha, beta))
 
 
 # Rows of 1- and 2-byte formats whose length is not a whole number of dwords
@@ -185,6 +190,8 @@ def test_unaligned_narrow_rows(dev, fmt, no_stage):
             ref = O.tvc(exact, xh, k, alpha=alpha, beta=beta, y=host(y0.to(torch.float32)))
             err = O.rel_err(host(out), ref)
             assert err <= TOL[fmt], (fmt, dims, k, alpha, beta, err)
+            mag = abs(alpha) * O.tvc(np.abs(exact), np.abs(xh), k) + abs(beta) * np.abs(host(y0))
+            assert_elementwise(host(out), ref, mag, dims[k], fmt, (dims, k, alpha, beta))
 
 
 # Small slabs staged through LDS in blocks of whole slabs: rows of 33-64
@@ -223,6 +230,8 @@ def test_staged_small_slabs(dev, fmt):
             ref = O.tvc(exact, xh, k, alpha=alpha, beta=beta, y=host(y0))
             err = O.rel_err(host(out), ref)
             assert err <= TOL[fmt], (fmt, dims, k, alpha, beta, err)
+            mag = abs(alpha) * O.tvc(np.abs(exact), np.abs(xh), k) + abs(beta) * np.abs(host(y0))
+            assert_elementwise(host(out), ref, mag, dims[k], fmt, (dims, k, alpha, beta))
 
 
 def test_staged_equals_unstaged_bitwise_on_integers(dev):
