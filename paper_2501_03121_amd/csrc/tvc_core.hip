@@ -1175,8 +1175,8 @@ __global__ __launch_bounds__(kRowswThreads) void k_rowsw(RowArgs<typename St<DT>
 // A slab l is the contiguous block A[l][0..M)[0..R) of E = M*R elements.  A
 // workgroup takes blocks of sb consecutive slabs (sb*E elements, a multiple
 // of 16 bytes, so every block starts 16-byte aligned): it copies a block
-// into LDS with 16-byte loads, each thread holding kStageVecs/256 of them,
-// issues the loads of its next block, and computes the current block's
+// into LDS with 16-byte loads, each of the NT threads holding kStageVecs/NT
+// of them, issues the loads of its next block, and computes the current block's
 // sb*R outputs from LDS while those loads are in flight.  G = 2^glog lanes
 // per output group split the contracted extent and combine with shuffles.
 // For 4- and 8-byte elements, when a slab row is a whole number of 16-byte
@@ -1192,27 +1192,18 @@ __global__ __launch_bounds__(kRowswThreads) void k_rowsw(RowArgs<typename St<DT>
 // before the compute and complete in order.
 constexpr int kStageBytes = 32768;
 __host__ __device__ constexpr i64 stage_wres(i64 M, i64 acc_bytes) { return (M * acc_bytes + 15) / 16 * 16; }
-// With the output window: staging buffer, window and threads per workgroup,
-// and workgroups per CU.  The staged kernel needs several blocks in flight
-// per CU more than long bursts: measured on gfx950 over Table 1's staged
-// modes, one 1024-thread workgroup with a 96 KB window per CU lost 10-20
-// points, four 256-thread workgroups with 8 KB windows gained 0-5.
-#ifndef TVC_STAGEW_THREADS
-#define TVC_STAGEW_THREADS 256
-#endif
-#ifndef TVC_STAGEW_BYTES
-#define TVC_STAGEW_BYTES 32768
-#endif
-#ifndef TVC_STAGEW_WIN
-#define TVC_STAGEW_WIN 8192
-#endif
-#ifndef TVC_STAGEW_BPC
-#define TVC_STAGEW_BPC 4
-#endif
-constexpr int kStagewThreads = TVC_STAGEW_THREADS;
-constexpr int kStagewBytes = TVC_STAGEW_BYTES;
-constexpr int kStageWinBytes = TVC_STAGEW_WIN;
-constexpr int kStagewBpc = TVC_STAGEW_BPC;
+// With the output window: staging buffer, window, threads per workgroup and
+// workgroups per CU, by element size.  Measured on gfx950 over Table 1's
+// staged modes: for 4- and 8-byte elements one 1024-thread workgroup per CU
+// with a 64 KB staging buffer and a 64 KB window beats four 256-thread
+// workgroups with 32 KB blocks and 8 KB windows by 5-10 points (float32
+// 10^9 mode 7: 59 -> 66%, 13^8 mode 6: 61 -> 70%, float64 10^9 mode 7:
+// 62 -> 69%), and a 96 KB window behind a 32 KB block loses 2-14; for E4M3
+// (32^6 mode 4) the four small workgroups keep 8 points more.
+struct StageCfg { int threads, bytes, win, bpc; };
+__host__ __device__ constexpr StageCfg stage_cfg(int eb) {
+  return eb >= 4 ? StageCfg{1024, 65536, 65536, 1} : StageCfg{256, 32768, 8192, 4};
+}
 
 template <typename Acc>
 struct StageArgs {
@@ -1229,9 +1220,10 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<typename St<DT>::Acc> a)
   typedef typename St<DT>::T T;
   constexpr int EB = (int)sizeof(T);
   constexpr int VE = VB == 0 ? 1 : VB / EB;   // columns per output group
-  constexpr int kStageVecs = (WIN ? kStagewBytes : kStageBytes) / 16;
+  constexpr StageCfg C = stage_cfg(EB);
+  constexpr int kStageVecs = (WIN ? C.bytes : kStageBytes) / 16;
   constexpr int PER = kStageVecs / NT;        // 16-byte loads per thread per block
-  constexpr int WE = kStageWinBytes / (int)sizeof(Acc);
+  constexpr int WE = C.win / (int)sizeof(Acc);
   __shared__ uint4 lds[kStageVecs];
   __shared__ __align__(16) Acc win[WIN ? WE : 1];
   const int tid = threadIdx.x;
@@ -1487,10 +1479,12 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
   // Small slabs: stage whole slabs through LDS where the slab kernel loses
   // coalescing (measured on gfx950 over the Table 1 shapes): slabs of at
   // most 4 KB whose right extent is ragged, not a power of two, or at most
-  // 2 units wide, or narrower than one 16-byte vector (where a slab lane
-  // would load one element: E4M3 8^10 mode 8, 8-byte rows, 16% of peak).
-  // Other power-of-two slab widths stay with the slab kernel, which is
-  // faster there.  Rows (R == 1) of 33-64 units are staged only in
+  // 2 units wide (4 in float64: 8^10 mode 8, 64-byte slab rows, 64 -> 71%;
+  // float32 rows of that width, 16^7 mode 5, lose 77 -> 68% staged), or
+  // narrower than one 16-byte vector (where a slab lane would load one
+  // element: E4M3 8^10 mode 8, 8-byte rows, 16% of peak).  Other
+  // power-of-two slab widths stay with the slab kernel, which is faster
+  // there.  Rows (R == 1) of 33-64 units are staged only in
   // float64, where the row kernel's double accumulators limit occupancy;
   // in the other formats the row kernel is 10-40% faster on them.  Rows
   // narrower than one 16-byte vector are staged in every format (the row
@@ -1499,7 +1493,7 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
   const i64 sbytes = M * R * b;
   const bool pow2 = (nu & (nu - 1)) == 0;
   const bool small = R == 1 ? ((dtype == TVC_F64 && p.vec && nu > 32 && nu <= 64) || (!p.vec && sbytes < 16))
-                            : (sbytes <= 4096 && nu <= 32 && (p.tail > 0 || !pow2 || nu <= 2 || !p.vec));
+                            : (sbytes <= 4096 && nu <= 32 && (p.tail > 0 || !pow2 || nu <= 2 || (b == 8 && nu <= 4) || !p.vec));
   if (a16 && small && !tuning().stage_off) {
     const i64 q = 16 / gcd_(16, sbytes);
     // Slabs per block in a staging buffer of the given size less the
@@ -1520,9 +1514,10 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
     };
     // with many blocks, outputs through the LDS window (a block's outputs at
     // most half of it), in blocks of the window variant's staging size
-    const i64 sbw = slabs(kStagewBytes);
+    const StageCfg sc = stage_cfg((int)b);
+    const i64 sbw = slabs(sc.bytes);
     const bool win = kWinOn && !tuning().win_off && sbw >= 1 &&
-                     cdiv(L, sbw) >= 4 * (i64)device_cus() && sbw * R * (i64)ab <= kStageWinBytes / 2;
+                     cdiv(L, sbw) >= 4 * (i64)device_cus() && sbw * R * (i64)ab <= sc.win / 2;
     const i64 sb = win ? sbw : slabs(kStageBytes);
     if (sb >= 1) {
       p.family = kStage;
@@ -1536,8 +1531,8 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
       const i64 ve = p.stage_vb == 0 ? 1 : p.stage_vb / b;
       p.nsplit = 1;
       p.tasks = cdiv(L, sb);
-      p.grid = grid_for(p.tasks, kStage, p.win ? kStagewBpc : 4);
-      const int nt = p.win ? kStagewThreads : kBlock;
+      p.grid = grid_for(p.tasks, kStage, p.win ? sc.bpc : 4);
+      const int nt = p.win ? sc.threads : kBlock;
       // lanes per output group: as many as keep all threads busy
       // (measured: a whole wave per row serialises the reductions)
       const i64 outs = std::max<i64>(sb * R / ve, 1);
@@ -1749,10 +1744,11 @@ hipError_t run_dt(const void* A, i64 L, i64 M, i64 R, const void* w_, void* y_, 
     StageArgs<Acc> a{A, w, y, L, M, R, p.sb, p.tasks, p.glog, (Acc)alpha, (Acc)beta, oscale, odiv};
     constexpr int VW = (DT == TVC_F32 || DT == TVC_F64) ? 16 : 4;
     if (p.win) {
-      const dim3 wblk(kStagewThreads);
+      constexpr int NT = stage_cfg((int)sizeof(typename St<DT>::T)).threads;
+      const dim3 wblk(NT);
       if (p.stage_vb != 0 && p.stage_vb == VW)
-        hipLaunchKernelGGL((k_stage<DT, ROLE, VW, kStagewThreads, true>), grd, wblk, 0, st, a);
-      else hipLaunchKernelGGL((k_stage<DT, ROLE, 0, kStagewThreads, true>), grd, wblk, 0, st, a);
+        hipLaunchKernelGGL((k_stage<DT, ROLE, VW, NT, true>), grd, wblk, 0, st, a);
+      else hipLaunchKernelGGL((k_stage<DT, ROLE, 0, NT, true>), grd, wblk, 0, st, a);
     } else {
       if (p.stage_vb != 0 && p.stage_vb == VW)
         hipLaunchKernelGGL((k_stage<DT, ROLE, VW, kBlock, false>), grd, blk, 0, st, a);

@@ -147,10 +147,11 @@ def test_batch_and_tuning_argument_errors():
     assert lib.tvc_contract_plan(t, 1, info, 9) == L.TVC_OK and info[0] == 1 and info[8] == 0
 
 
-# The staged kernel copies blocks of whole slabs into a 32 KB LDS buffer
-# whose end holds the M weights (accumulator type, 16-byte aligned), and
-# loads a block with 16-byte vectors; with the output window (8 KB) a
-# block's outputs take at most half of it.  The planner's block sizes must
+# The staged kernel copies blocks of whole slabs into an LDS buffer (32 KB;
+# 64 KB with the output window for 4- and 8-byte elements) whose end holds
+# the M weights (accumulator type, 16-byte aligned), and loads a block with
+# 16-byte vectors; with the output window (64 KB for 4- and 8-byte elements,
+# else 8 KB) a block's outputs take at most half of it.  The planner's block sizes must
 # keep all of that in bounds, for every format and many slab shapes.
 def test_staged_blocks_fit_their_lds():
     import itertools
@@ -180,7 +181,8 @@ def test_staged_blocks_fit_their_lds():
                 block = sb * M * R * eb[dt]
                 wres = (M * ab[dt] + 15) // 16 * 16
                 assert sb >= 1 and block % 16 == 0, (dims, dt, k, sb)
-                assert block + wres <= 32768, (dims, dt, k, sb, block, wres)
+                wide = eb[dt] >= 4 and info[8]
+                assert block + wres <= (65536 if wide else 32768), (dims, dt, k, sb, block, wres)
                 if info[8]:
-                    assert sb * R * ab[dt] <= 4096, (dims, dt, k, sb)
+                    assert sb * R * ab[dt] <= (32768 if wide else 4096), (dims, dt, k, sb)
     assert seen > 100

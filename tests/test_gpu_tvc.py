@@ -349,8 +349,8 @@ def test_windowed_rows_and_slabs(dev, fmt):
             tune.set_tuning("stage", -1)
         try:
             p = tvc.contract_plan(A, k, scale=S)
-            # a staged block's outputs must fit half of its 8 KB window: the
-            # narrow formats' 32 KB blocks of 9 x 14 or 9 x 20 slabs do not
+            # a staged block's outputs must fit half of its window, 8 KB for
+            # the narrow formats: their 32 KB blocks of 9 x 14 or 9 x 20 slabs do not
             want_win = family != "stage" or fmt in ("f32", "f64")
             assert p["family"] == family and p["window"] == want_win, (fmt, dims, k, p)
             x, xh = vec(dims[k], 30 + k, fmt, dev)
