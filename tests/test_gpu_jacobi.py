@@ -124,3 +124,21 @@ def test_jacobi_full_size_sweep(dev, dims):
     del A
     torch.cuda.empty_cache()
     check(traj, Ah, x0, 1e-5, form="kron")
+
+
+# Tensors whose one-pass strips outnumber the waves of a 256-CU part (rows
+# of more than 2^20 16-byte units, split as n0 n1 x the rest): the rows are
+# then not split into chunks, and the tasks run in more than one round; the
+# last unit of a row is ragged in all but the first.
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("fmt,dims", [("f32", (8, 8, 4200000)), ("f32", (8, 9, 2049, 2049)),
+                                      ("f64", (8, 8, 4200000)), ("f64", (9, 9, 1451, 1451))],
+                         ids=["f32-8x8x4200000", "f32-8x9x2049x2049", "f64-8x8x4200000", "f64-9x9x1451x1451"])
+def test_jacobi_strips_beyond_one_round(dev, fmt, dims):
+    A, a = synth.device_planted(dims, 10.0, 0.1, 200, dev, dtype=torch.float64 if fmt == "f64" else None)
+    x0 = synth.warm_start(a, 0.9, 400)
+    traj = run_jacobi(A, x0, 2, dev)
+    Ah = A.cpu().numpy()
+    del A
+    torch.cuda.empty_cache()
+    check(traj, Ah, x0, 1e-10 if fmt == "f64" else 1e-5, form="kron")
