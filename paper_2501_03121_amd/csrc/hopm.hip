@@ -270,15 +270,31 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailProg<Acc> p) {
       // out[r] = sum_i in[r * n + i] * w[i]; G lanes per row
       const i64 rows = q.a, n = q.b;
       const Acc* w = p.wv + p.woff[q.mode];
+      // G lanes per row: up to the row's length (at most a wave), but no
+      // more than lets every row into one pass of the workgroup where that
+      // leaves at least 8 (a pass waits for its loads; in global memory
+      // that is a round trip per pass)
       int G = 1;
       while (G < kWave && G < n) G <<= 1;
+      while (G > 8 && (i64)(kTailThreads / G) < rows) G >>= 1;
       const int sub = tid & (G - 1);
       const int grp = tid / G, ngrp = kTailThreads / G;
       for (i64 r0 = 0; r0 < rows; r0 += ngrp) {
         const i64 r = r0 + grp;
         Acc acc = (Acc)0;
-        if (r < rows)
-          for (i64 i = sub; i < n; i += G) acc = fma(in[r * n + i], w[i], acc);
+        if (r < rows) {
+          const Acc* row = in + r * n;
+          i64 i = sub;
+          for (; i + 3 * G < n; i += 4 * G) {   // four loads issued, then summed in order
+            const Acc v0 = row[i], v1 = row[i + G], v2 = row[i + 2 * G], v3 = row[i + 3 * G];
+            const Acc w0 = w[i], w1 = w[i + G], w2 = w[i + 2 * G], w3 = w[i + 3 * G];
+            acc = fma(v0, w0, acc);
+            acc = fma(v1, w1, acc);
+            acc = fma(v2, w2, acc);
+            acc = fma(v3, w3, acc);
+          }
+          for (; i < n; i += G) acc = fma(row[i], w[i], acc);
+        }
         for (int o = G >> 1; o >= 1; o >>= 1) acc += shfl_xor(acc, o);
         if (sub == 0 && r < rows) out[r] = acc;
       }
@@ -288,7 +304,15 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailProg<Acc> p) {
       const Acc* w = p.wv + p.woff[q.mode];
       for (i64 c = tid; c < rest; c += kTailThreads) {
         Acc acc = (Acc)0;
-        for (i64 i = 0; i < n; ++i) acc = fma(in[i * rest + c], w[i], acc);
+        i64 i = 0;
+        for (; i + 8 <= n; i += 8) {   // eight loads issued, then summed in order
+          Acc v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = in[(i + u) * rest + c];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc = fma(v[u], w[i + u], acc);
+        }
+        for (; i < n; ++i) acc = fma(in[i * rest + c], w[i], acc);
         out[c] = acc;
       }
     } else if (q.op == kTNorm) {
