@@ -176,18 +176,25 @@ template <typename Acc>
 __global__ __launch_bounds__(256) void k_kron_chunked(const double* x, KronArgs k, int h, i64 B, Acc* w,
                                                       i64 n) {
   __shared__ double lo[kKronLo];
-  for (i64 j = threadIdx.x; j < B; j += blockDim.x) {
-    i64 rem = j;
-    double p = 1.0;
-    for (int m = k.nm - 1; m >= k.nm - h; --m) {
-      i64 q, i;
-      divmod(rem, k.dims[m], q, i);
-      rem = q;
-      p *= x[k.offs[m] + i];
-    }
-    lo[j] = p;
-  }
+  // The table one mode at a time, last mode first (its index varies
+  // fastest): entries i * len + j of the next table are entry j of the
+  // current one times x_m[i], the same products in the same order as one
+  // mode after another per entry.  In place: i >= 1 first, then i = 0.
+  if (threadIdx.x == 0) lo[0] = 1.0;
   __syncthreads();
+  int len = 1;
+  for (int m = k.nm - 1; m >= k.nm - h; --m) {
+    const double* xm = x + k.offs[m];
+    const int dm = (int)k.dims[m];
+    for (int t = threadIdx.x; t < (dm - 1) * len; t += blockDim.x) {
+      const int i = 1 + t / len, j = t % len;
+      lo[i * len + j] = lo[j] * xm[i];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < len; j += blockDim.x) lo[j] *= xm[0];
+    __syncthreads();
+    len *= dm;
+  }
   const i64 nchunks = n / B;
   for (i64 c = blockIdx.x; c < nchunks; c += gridDim.x) {
     i64 rem = c;
