@@ -1646,14 +1646,19 @@ TvcPlan plan_tvc(int dtype, i64 L, i64 M, i64 R, bool a4, bool w4, bool a16) {
         // with the window, 4 units per lane where rows are a multiple of
         // 64 KB apart and less than 64 MB (measured on 32^6: float32 mode 1,
         // 4 MB rows, 75 -> 79%, bf16 mode 2, 64 KB rows, 81 -> 86%; 4 KB rows
-        // and 64-128 MB rows lose 2-4% with 4); else 2 for M >= 32 (Table
+        // and 64-128 MB rows lose 2-4% with 4); else, for M >= 32, 2 (Table
         // 1's odd row pitches, one unit per lane against two: float64 63^5
         // modes 0-1 71 -> 80%, 175^4 mode 1 78 -> 83%, float32 63^5 mode 1
-        // 79 -> 83%; 32^6 modes 0 and 3 even; 4 gains up to 3 more points
-        // on float64 63^5 but loses 1-3 elsewhere) and 1 for shorter M,
-        // where 2 lost (10^9 modes 0-4 75 -> 71%, 8^10 mode 1 77 -> 71%)
+        // 79 -> 83%; 32^6 modes 0 and 3 even; 4 loses 1-3 points on
+        // float32 and bf16) or 4 for float64 rows that are not a multiple
+        // of 4 KB apart (63^5 modes 0-2 80 -> 82-85%, 175^4 mode 1 83 ->
+        // 84%, mode 0 83 -> 82%); 1 for shorter M, where 2 lost (10^9
+        // modes 0-4 75 -> 71%, 8^10 mode 1 77 -> 71%)
         const i64 pitch = R * b;
-        const int cmax = !win ? 4 : ((pitch % 65536 == 0 && pitch < ((i64)64 << 20)) ? 4 : M >= 32 ? 2 : 1);
+        const int cmax = !win ? 4
+                         : (pitch % 65536 == 0 && pitch < ((i64)64 << 20)) ? 4
+                         : M < 32 ? 1
+                         : (b == 8 && pitch % 4096 != 0) ? 4 : 2;
         for (int cpt = cmax; cpt >= 1; cpt /= 2) {
           const i64 strips = L * cdiv(nu, (i64)kWave * cpt);
           const bool fits = !win || (i64)wv * kWave * cpt * epv * (i64)ab <= kWinBytes / 2;
