@@ -74,6 +74,37 @@ def test_table1_full_size_sampled(dev, n, d):
     torch.cuda.empty_cache()
 
 
+# float64 at the paper's Table 1 element counts (6.6-8.6 GB), on the tensors
+# whose float64 plans differ from float32's: column strips of four units per
+# lane on odd row pitches (175^4, 63^5), the staged kernel with 64 KB blocks
+# (10^9 modes 6-7) and with 4-unit slab rows (8^10 mode 8); sampled outputs of
+# every mode as above, each within the float64 rounding bound of its dot product
+F64_TABLE1 = [(175, 4), (63, 5), (10, 9), (8, 10)]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("n,d", F64_TABLE1, ids=[f"{n}^{d}" for n, d in F64_TABLE1])
+def test_table1_full_size_sampled_f64(dev, n, d):
+    dims = (n,) * d
+    A = synth.device_normal(dims, 40 + d, dev, dtype=torch.float64)
+    Ah = A.cpu().numpy()
+    Aabs = np.abs(Ah)
+    for k in range(d):
+        xh = synth.unit_vectors([n], 50 + k)[0]
+        y = tvc.contract(A, torch.from_numpy(xh).to(dev), k)
+        u, _, v = O.matricized_dims(dims, k)
+        g = synth.rng(60 + k)
+        lr = np.stack([g.integers(0, u, SAMPLES), g.integers(0, v, SAMPLES)], axis=1)
+        lr = np.concatenate([lr, [[0, 0], [u - 1, v - 1]]])
+        got = host(y).reshape(u, v)[lr[:, 0], lr[:, 1]]
+        ref = O.tvc_sample(Ah, xh, k, lr)
+        ref_abs = O.tvc_sample(Aabs, np.abs(xh), k, lr)
+        assert_elementwise(got, ref, ref_abs, n, "f64", (dims, k))
+        del y
+    del A
+    torch.cuda.empty_cache()
+
+
 def run_sweeps(A, x0, sweeps, dev, scale=None):
     x = tvc.pack_vectors(x0, dev)
     out = []
