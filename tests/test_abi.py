@@ -186,3 +186,36 @@ def test_staged_blocks_fit_their_lds():
                 if info[8]:
                     assert sb * R * ab[dt] <= (32768 if wide else 4096), (dims, dt, k, sb)
     assert seen > 100
+
+
+# The planner's choices on the benchmark and Table 1 shapes for a 256-CU
+# part (the count the library assumes without a device), as measured on the
+# MI355X: the width of the windowed column strips by row pitch, M and
+# format, and where small slabs are staged.  (family, window, units per lane
+# of the strips, row rotation, staged slabs > 0)
+PLAN_CASES = [
+    ((32,) * 6, 1, L.TVC_F32, ("col", 1, 4, 1, False)),    # 4 MB rows: 4 units, rotated
+    ((32,) * 6, 0, L.TVC_F32, ("col", 1, 2, 0, False)),    # 128 MB rows, M >= 32: 2
+    ((32,) * 6, 3, L.TVC_F32, ("col", 1, 2, 0, False)),    # 4 KB rows: 2
+    ((32,) * 6, 4, L.TVC_F32, ("slab", 1, 0, 0, False)),
+    ((32,) * 6, 5, L.TVC_F32, ("row", 1, 0, 0, False)),
+    ((63,) * 5, 0, L.TVC_F32, ("col", 1, 2, 0, False)),    # odd pitch, M >= 32: 2
+    ((63,) * 5, 0, L.TVC_F64, ("col", 1, 4, 1, False)),    # float64, not a multiple of 4 KB: 4
+    ((10,) * 9, 0, L.TVC_F32, ("col", 1, 1, 0, False)),    # M < 32: 1
+    ((10,) * 9, 7, L.TVC_F32, ("stage", 1, 0, 0, True)),
+    ((8,) * 10, 8, L.TVC_F32, ("stage", 1, 0, 0, True)),   # 2-unit slab rows
+    ((8,) * 10, 8, L.TVC_F64, ("stage", 1, 0, 0, True)),   # 4-unit rows, float64 only
+    ((16,) * 7, 5, L.TVC_F32, ("slab", 1, 0, 0, False)),   # 4-unit rows, float32: slab kernel
+    ((32,) * 6, 4, L.TVC_F8E4M3, ("stage", 1, 0, 0, True)),
+]
+
+
+def test_plans_of_benchmark_and_table1_shapes():
+    fam = ("row", "col", "slab", "stage")
+    for dims, k, dt, want in PLAN_CASES:
+        scale = (1 << 21) if dt == L.TVC_F8E4M3 else None
+        t = tensor(dims, dtype=dt, data=1 << 20, scale=scale)
+        info = (ctypes.c_int32 * 12)()
+        assert L.lib().tvc_contract_plan(t, k, info, 12) == L.TVC_OK
+        got = (fam[info[0]], info[8], info[9], info[10], info[11] > 0)
+        assert got == want, (dims, k, dt, got, want)
